@@ -1,0 +1,98 @@
+"""Seeded synthetic workloads shaped like the paper's examples.
+
+This module only draws initial fields and names parameters; it holds none of the
+method's arithmetic.  Both the GPU path and the CPU oracle read their inputs from
+here, so the two sides always see the same bytes.
+
+Random fields: numpy ``default_rng(seed).uniform(lo, hi, (N, N))`` in FP64
+(PCG64).  For the two-species system the u-field is drawn first, then the
+v-field, from the same generator.
+"""
+import math
+
+import numpy as np
+
+PERIODIC = "periodic"
+NEUMANN = "neumann"
+
+# Named configurations.  Parameters follow the equations of the paper
+# (Allen-Cahn Sec. 3.1 with a = lambda = eps^2, b = 1; Cahn-Hilliard Sec. 3.2;
+# Schnakenberg Sec. 3.4.1) on the unit square.
+CONFIGS = {
+    "ac64": dict(kind="allen_cahn", N=64, L=1.0, bc=PERIODIC, diff=(0.05 ** 2,), b=1.0,
+                 ht=1e-2, steps=10, init=("uniform", -0.9, 0.9), seed=0,
+                 tol=1e-10, tau=0.9, omega=1.0),
+    "ac2048": dict(kind="allen_cahn", N=2048, L=1.0, bc=PERIODIC, diff=(0.01 ** 2,), b=1.0,
+                   ht=1e-3, steps=200, init=("uniform", -0.1, 0.1), seed=1,
+                   tol=1e-6, tau=0.9, omega=1.0),
+    "ch512": dict(kind="cahn_hilliard", N=512, L=1.0, bc=NEUMANN, diff=(0.02 ** 2,), b=1.0,
+                  ht=1e-4, steps=500, init=("uniform", -0.05, 0.05), seed=2,
+                  tol=1e-2, tau=0.7, omega=1.0),
+    "schnak1024": dict(kind="schnakenberg", N=1024, L=1.0, bc=PERIODIC, diff=(1.0, 10.0),
+                       a=0.1, sb=0.9, kappa=1.0, ht=1e-3, steps=100,
+                       init=("steady_plus_uniform", -0.01, 0.01), seed=3,
+                       tol=1e-4, tau=0.9, omega=1.0),
+}
+
+SERVING_SIZES = (64, 128, 256, 512, 1024)
+
+
+def uniform_field(N, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, (N, N))
+
+
+def initial_field(cfg, N=None, seed=None):
+    """The initial state of a named configuration (optionally resized / reseeded)."""
+    N = cfg["N"] if N is None else N
+    seed = cfg["seed"] if seed is None else seed
+    kind, lo, hi = cfg["init"]
+    if kind == "uniform":
+        return uniform_field(N, lo, hi, seed)
+    if kind == "steady_plus_uniform":
+        rng = np.random.default_rng(seed)
+        a, b = cfg["a"], cfg["sb"]
+        u = (a + b) + rng.uniform(lo, hi, (N, N))
+        v = b / (a + b) ** 2 + rng.uniform(lo, hi, (N, N))
+        return np.stack([u, v])
+    raise ValueError(kind)
+
+
+def serving_requests(n_traj=64, steps_per_traj=8, seed=5, sizes=SERVING_SIZES, rate=None):
+    """The mixed serving stream: trajectories of random equation / size / BC / h_t.
+
+    Each trajectory draws its equation uniformly from the three named equation
+    configs, N uniformly from ``sizes``, periodic or Neumann 50/50 and h_t
+    log-uniform on [1e-4, 1e-2] (Cahn-Hilliard clamped to <= lambda / 4, where its
+    step has a unique root).  Arrival times are Poisson with the given rate
+    (requests per second), or all zero.
+    """
+    rng = np.random.default_rng(seed)
+    eqs = ["ac2048", "ch512", "schnak1024"]
+    out = []
+    t = 0.0
+    for tid in range(n_traj):
+        base = dict(CONFIGS[eqs[int(rng.integers(0, 3))]])
+        N = int(sizes[int(rng.integers(0, len(sizes)))])
+        bc = PERIODIC if rng.random() < 0.5 else NEUMANN
+        ht = float(10.0 ** rng.uniform(-4.0, -2.0))
+        if base["kind"] == "cahn_hilliard":
+            ht = min(ht, base["diff"][0] / 4.0)
+        base.update(N=N, bc=bc, ht=ht, steps=steps_per_traj)
+        u0 = initial_field(base, N=N, seed=int(seed * 100003 + tid))
+        arrivals = []
+        for _ in range(steps_per_traj):
+            if rate:
+                t += float(rng.exponential(1.0 / rate))
+            arrivals.append(t)
+        out.append(dict(cfg=base, u0=u0, arrivals=arrivals, traj=tid))
+    return out
+
+
+def grid_points(cfg):
+    return int(cfg["N"]) ** 2
+
+
+def log2_exact(n):
+    k = int(round(math.log2(n)))
+    return k if 2 ** k == n else None

@@ -1,0 +1,181 @@
+/*
+ * rd.h -- C ABI of librdpdhg: one implicit reaction-diffusion time step solved by
+ * the G-prox linearized PDHG iteration on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: Liu, Liu, Osher, Li, "A first-order computational algorithm for
+ * reaction-diffusion type equations via primal-dual hybrid gradient method"
+ * (arXiv 2305.03945).  Given U^k, the step size h_t, the operator, the reaction
+ * and the boundary condition, a step returns U^{k+1}, the root of F(U) = 0 for
+ * the backward-Euler scheme (Sec. 2.1, eqs. 11-12; Sec. 3.2, eq. 29; Sec. 3.4.1),
+ * computed by Algorithm 1:
+ *
+ *     P_{n+1} = P_n + tau_p G^-1 F(U_n)
+ *     P~      = P_{n+1} + omega (P_{n+1} - P_n)
+ *     U_{n+1} = U_n - tau_u grad F(U_n)^T P~
+ *
+ * from U_0 = U^k, P_0 = 0, stopped when ||Res(U_n)||_2 <= tol with Res = F / h_t
+ * (Sec. 2.1, "Stopping criterion"; for two components the component norms are
+ * added, Sec. 3.4.1).  G = (I - alpha Lap + beta Lap^2)^2 is inverted by a 2-D FFT
+ * (periodic grids) or a 2-D DCT-II (Neumann grids, Remark 1).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments documented as DEVICE are device (HBM) pointers; HOST ones are
+ *     host pointers.  Fields are FP64, layout [ncomp][N][N], row-major, x fastest.
+ *   - The caller owns every array it passes; the library owns its workspaces.
+ *   - Functions return rd_status; nothing throws across the ABI.
+ *   - A context is not thread-safe: one host thread per context.
+ *   - Work is enqueued on the HIP stream passed in (NULL = the default stream);
+ *     functions that return results in host memory synchronise that stream.
+ */
+#ifndef RD_PDHG_H
+#define RD_PDHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RD_OK = 0,
+    RD_E_INVALID = -1,    /* bad argument: shape, N not a power of two in [16, 4096], h_t <= 0,
+                             unsupported operator / reaction pair, NULL pointer             */
+    RD_E_NOCONV = -2,     /* max_iter (or max_outer) reached; the last iterate is returned   */
+    RD_E_NONFINITE = -3,  /* residual NaN/Inf or grown beyond 1e8 x its initial value: the
+                             divergence the paper reports for h_t above a threshold (Sec. 2.2) */
+    RD_E_NOMEM = -4,      /* device allocation failed, or serving budget exceeded           */
+    RD_E_DEVICE = -5,     /* a HIP runtime call failed                                      */
+    RD_E_BUSY = -6        /* serving: the ticket is not finished yet                        */
+} rd_status;
+
+typedef enum { RD_BC_PERIODIC = 0, RD_BC_NEUMANN = 1 } rd_bc;
+
+/* Linear operator of F.  RD_OP_LAP5: +lambda Lap with the 5-point Laplacian (Sec. 2.1;
+ * periodic block-circulant form, or the Neumann L_1/L_2 form of Remark 1, eq. 24).
+ * RD_OP_BIHARM13: -lambda Lap Lap with the 13-point stencil (= 5-point squared; Sec. 3.2). */
+typedef enum { RD_OP_LAP5 = 0, RD_OP_BIHARM13 = 1 } rd_operator;
+
+/* Reaction term.  Parameters in rd_problem.p[]:
+ *   RD_RX_NONE          linear step (heat with LAP5, biharmonic with BIHARM13)
+ *   RD_RX_ALLEN_CAHN    p[0] = b:  f(u) = b (u - u^3)           (Sec. 3.1, eq. 25), LAP5 only
+ *   RD_RX_CAHN_HILLIARD p[0] = b:  + Lap (b (u^3 - u))          (Sec. 3.2, eq. 28), BIHARM13 only
+ *   RD_RX_SCHNAKENBERG  p[0] = a, p[1] = b, p[2] = kappa; two components (u, v) with
+ *                       diffusion diff[0], diff[1]                (Sec. 3.4.1), LAP5 only      */
+typedef enum {
+    RD_RX_NONE = 0,
+    RD_RX_ALLEN_CAHN = 1,
+    RD_RX_CAHN_HILLIARD = 2,
+    RD_RX_SCHNAKENBERG = 3
+} rd_reaction_kind;
+
+typedef struct {
+    int32_t nx, ny;          /* grid points per side; must be equal, power of two, 16..4096 */
+    double lx, ly;           /* side lengths; must be equal; spacing h = lx / nx            */
+    int32_t bc;              /* rd_bc                                                       */
+    int32_t op;              /* rd_operator                                                 */
+    int32_t rx;              /* rd_reaction_kind                                            */
+    int32_t pad0;
+    double diff[2];          /* lambda (diff[0]) or (D1, D2) for two components            */
+    double p[4];             /* reaction parameters, see rd_reaction_kind                   */
+} rd_problem;
+
+typedef enum { RD_FP64 = 0, RD_FP32_MIXED = 1 } rd_precision;
+typedef enum { RD_INIT_PREV = 0, RD_INIT_PROX = 1 } rd_init;
+
+typedef struct {
+    double tol;              /* stop when ||F(U)/h_t||_2 (summed over components) <= tol   */
+    int32_t max_iter;        /* PDHG iterations per step (FP64), or inner iterations per outer
+                                pass (mixed)                                                 */
+    int32_t max_outer;       /* mixed only: outer FP64 correction passes                     */
+    double tau_u, tau_p;     /* PDHG step sizes                                              */
+    double omega;            /* extrapolation coefficient (the paper uses 1, Sec. 3)         */
+    int32_t precision;       /* rd_precision                                                 */
+    int32_t init;            /* rd_init: U_0 = U^k (paper) or the pointwise reaction prox    */
+    double inner_rtol;       /* mixed only: inner solve stops at ||F~(e)|| <= inner_rtol ||r|| */
+} rd_opts;
+
+typedef struct {
+    int32_t iters;           /* PDHG iterations (mixed: FP32 inner iterations, all passes)    */
+    int32_t outer;           /* mixed: FP64 outer passes; FP64 path: 0                        */
+    double residual_l2;      /* final ||F(U)/h_t||_2 (paper norm, FP64)                       */
+    double residual0;        /* the same at U_0                                               */
+    double mass_drift;       /* sum(U^{k+1} - U^k) in FP64, per step (component 0 + 1)        */
+    int32_t status;          /* rd_status of the step                                         */
+    int32_t pad0;
+} rd_info;
+
+/* ---- context ---------------------------------------------------------------------- */
+/* Create a context on HIP device `device`.  *out receives the handle.                    */
+rd_status rd_create(int device, void **out);
+/* Free every workspace and table of the context.                                         */
+rd_status rd_destroy(void *ctx);
+
+/* Default options: tol 1e-10, max_iter 10000, max_outer 20, tau_u = tau_p = 0.9,
+ * omega = 1, FP64, U_0 = U^k, inner_rtol 1e-3.                                             */
+void rd_default_opts(rd_opts *opts);
+
+/* Device bytes one step's workspace needs (fields, spectra, partial sums).              */
+size_t rd_footprint_bytes(const rd_problem *prob, const rd_opts *opts);
+
+/* ---- one implicit step (Algorithm 1, the body of its time loop) --------------------- */
+/* u_n (DEVICE, read) -> u_np1 (DEVICE, written); they may alias.  hip_stream is a
+ * hipStream_t or NULL.  info (HOST) receives iteration count, residuals, mass drift and
+ * status; the return value equals info->status, or an argument/device error code.
+ * Synchronises the stream.                                                               */
+rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
+                  const double *u_n, double *u_np1, void *hip_stream, rd_info *info);
+
+/* ---- kernel-level entry points (the pieces of one iteration) ------------------------ */
+/* W = F(U) (Sec. 2.1 eq. 12; Sec. 3.2 eq. 29; Sec. 3.4.1).  u, uk, w: DEVICE, [c][N][N].
+ * *res_l2 (HOST) receives ||W / h_t||_2 summed over components.  Synchronises.          */
+rd_status rd_residual(void *ctx, const rd_problem *prob, double h_t, const double *u,
+                      const double *uk, double *w, void *hip_stream, double *res_l2);
+/* Y = G^-1 W with G = (I - alpha Lap + beta Lap^2)^2 per component as the equation
+ * implies (Sec. 2.1 "Choosing the matrix G"; Remark 1 for Neumann).  w, y: DEVICE.
+ * precision RD_FP64 or RD_FP32_MIXED (FP32 transforms).  Synchronises.                    */
+rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_t precision,
+                           const double *w, double *y, void *hip_stream);
+/* Pointwise reaction prox (the implicit reaction-only step, a predictor for U_0;
+ * Sec. 2.1 "Initial guess"): Allen-Cahn cubic, Schnakenberg 2x2; identity otherwise.
+ * c, u: DEVICE.  Synchronises.                                                            */
+rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *c, double *u,
+                  void *hip_stream);
+
+/* ---- instrumentation ------------------------------------------------------------- */
+/* Time the four kernels of one Algorithm-1 iteration in isolation on hip_stream:
+ * prepares the step for u_n (DEVICE) like rd_step, then launches each kernel `reps`
+ * times, each launch bracketed by its own pair of HIP events on that stream, with the
+ * slot's iteration state reset before every launch.  ms_out (HOST, 4 doubles) receives
+ * the mean launch durations in milliseconds of: column pass, inverse row pass + dual
+ * update, primal update, residual + forward row pass.  Synchronises.                    */
+rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
+                               const double *u_n, int32_t reps, void *hip_stream, double *ms_out);
+
+/* ---- serving: continuous batching of steps of resident trajectories ----------------- */
+/* Set the device-memory budget for resident trajectories (bytes; 0 = unlimited).         */
+rd_status rd_serve_set_budget(void *ctx, size_t bytes);
+/* Open a trajectory: copies u0 (DEVICE) to resident state.  Does not reserve memory yet:
+ * it is admitted (memory reserved) by rd_serve_pump when the budget allows.              */
+rd_status rd_traj_open(void *ctx, const rd_problem *prob, const rd_opts *opts,
+                       const double *u0, void *hip_stream, void **out);
+/* Queue one implicit step of size h_t; *ticket (HOST) identifies it.  Steps of one
+ * trajectory run in submission order.                                                     */
+rd_status rd_traj_submit(void *traj, double h_t, uint64_t *ticket);
+/* Admit queued work as budget and slots allow, advance every running step by one batched
+ * launch round, retire finished steps.  Returns after one round (or max_wait_us).         */
+rd_status rd_serve_pump(void *ctx, int32_t max_wait_us);
+/* RD_E_BUSY until the ticket's step finished; then fills info (HOST) and returns its
+ * status.                                                                                 */
+rd_status rd_poll(void *ctx, uint64_t ticket, rd_info *info);
+/* Copy the trajectory's current state to u_out (DEVICE).  Synchronises.                   */
+rd_status rd_traj_read(void *traj, double *u_out, void *hip_stream);
+/* Close a trajectory and release its resident memory.                                    */
+rd_status rd_traj_close(void *traj);
+
+const char *rd_status_str(rd_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RD_PDHG_H */

@@ -1,0 +1,695 @@
+// HIP kernels of one G-prox PDHG iteration (Algorithm 1) and of the FP64 outer
+// residual passes of the mixed-precision step.
+//
+// One iteration n -> n+1 is four launches over every active slot:
+//   k_cols       column pass of Y = G^-1 W_n: forward column FFT, multiply by
+//                1 / (N^2 g), inverse column FFT, in place on the spectrum S
+//                (the row pass before it left S = row transforms of W_n).
+//   k_rowinv     inverse row transform -> Y_n;  P_{n+1} = P_n + tau_p Y_n,
+//                P~ = P_{n+1} + omega (P_{n+1} - P_n)   (eqs. 21-22)
+//   k_upd        U_{n+1} = U_n - tau_u grad F(U_n)^T P~ (eq. 23 / 32 / Sec. 3.4.1),
+//                reaction derivative at the old U_n
+//   k_row_forward W_{n+1} = F(U_{n+1}), its squared norm, the forward row
+//                transform into S; the last workgroup to finish reduces the
+//                per-workgroup partial sums in a fixed order and takes the stop
+//                decision for the slot (Sec. 2.1 stopping criterion).
+// Every kernel first reads the slot's State and returns at once when the slot
+// is finished, so a host may enqueue more iterations than needed.
+#pragma once
+#include "fft.h"
+
+namespace rdk {
+
+// ---------------------------------------------------------------- kinds of row-forward pass
+enum {
+    K_INIT64 = 0,     // FP64 path: U_0 from u_n, U^k copy, W_0 = F(U_0)
+    K_ITER64 = 1,     // FP64 path: W_{n+1} = F(U_{n+1})
+    K_INNER32 = 2,    // mixed: W = F~(e_{n+1}) in FP32
+    K_OUTER_INIT = 3, // mixed: U from u_n, r = F(U) in FP64, inner loop starts
+    K_OUTER_UPD = 4   // mixed: U += e (FP64), r = F(U) in FP64, next inner loop
+};
+
+template <typename T> __device__ __forceinline__ T ldg(const T *p) { return *p; }
+
+// ---------------------------------------------------------------- pointwise reaction prox
+// Implicit reaction-only step at one point (predictor for U_0): Allen-Cahn
+// u + h_t b (u^3 - u) = c by Newton from u = c (strictly increasing when
+// h_t b < 1); Schnakenberg by eliminating v and Newton on u.  Fixed iteration
+// counts keep the result independent of the data.
+__device__ __forceinline__ double prox_ac(double c, double ht, double b) {
+    const double al = ht * b, be = 1.0 - ht * b;
+    double u = c;
+#pragma unroll 1
+    for (int i = 0; i < 40; ++i) u -= (al * u * u * u + be * u - c) / (3.0 * al * u * u + be);
+    return u;
+}
+__device__ __forceinline__ void prox_schnak(double cu, double cv, double ht, double a, double b, double kap,
+                                            double &u, double &v) {
+    const double gam = ht * kap, B = cv + gam * b;
+    u = cu;
+#pragma unroll 1
+    for (int i = 0; i < 40; ++i) {
+        const double d = 1.0 + gam * u * u;
+        const double phi = u - cu - gam * (a - u + u * u * B / d);
+        const double dphi = 1.0 + gam - gam * B * 2.0 * u / (d * d);
+        u -= phi / dphi;
+    }
+    v = B / (1.0 + gam * u * u);
+}
+
+// ---------------------------------------------------------------- equation residuals
+// Field accessors return the value of component c at (y + dy, x + dx) with the
+// boundary mapping already applied by the caller-provided functor.
+
+// F(U) in precision V (Sec. 2.1 eq. 12; Sec. 3.2 eq. 29 with the PDE's sign of the
+// biharmonic term; Sec. 3.4.1).  ukc: U^k at the point, per component.
+template <int EQ, typename V, class Acc>
+__device__ __forceinline__ void eval_F(const Slot &s, Acc u, const V *ukc, V *W, V *Uc) {
+    const V ht = (V)s.ht, ih2 = (V)s.inv_h2;
+    if constexpr (EQ == EQ_LAP5) {
+        const V u0 = u(0, 0, 0);
+        const V lap = (u(0, 0, -1) + u(0, 0, 1) + u(0, -1, 0) + u(0, 1, 0) - (V)4 * u0) * ih2;
+        const V b = (V)s.b;
+        W[0] = u0 - ukc[0] - ht * ((V)s.diff[0] * lap + b * (u0 - u0 * u0 * u0));
+        Uc[0] = u0;
+    } else if constexpr (EQ == EQ_BIH) {
+        const V u0 = u(0, 0, 0);
+        const V ul = u(0, 0, -1), ur = u(0, 0, 1), uu = u(0, -1, 0), ud = u(0, 1, 0);
+        const V axis1 = ul + ur + uu + ud;
+        const V diag = u(0, -1, -1) + u(0, -1, 1) + u(0, 1, -1) + u(0, 1, 1);
+        const V axis2 = u(0, 0, -2) + u(0, 0, 2) + u(0, -2, 0) + u(0, 2, 0);
+        const V lap13 = ((V)20 * u0 - (V)8 * axis1 + (V)2 * diag + axis2) * (V)s.inv_h4;
+        const V b = (V)s.b;
+        auto g = [b](V v) { return b * (v * v * v - v); };
+        const V lapg = (g(ul) + g(ur) + g(uu) + g(ud) - (V)4 * g(u0)) * ih2;
+        W[0] = u0 - ukc[0] + (V)s.diff[0] * ht * lap13 - ht * lapg;
+        Uc[0] = u0;
+    } else {
+        const V u0 = u(0, 0, 0), v0 = u(1, 0, 0);
+        const V lu = (u(0, 0, -1) + u(0, 0, 1) + u(0, -1, 0) + u(0, 1, 0) - (V)4 * u0) * ih2;
+        const V lv = (u(1, 0, -1) + u(1, 0, 1) + u(1, -1, 0) + u(1, 1, 0) - (V)4 * v0) * ih2;
+        const V kap = (V)s.kappa, u2v = u0 * u0 * v0;
+        W[0] = u0 - ukc[0] - ht * ((V)s.diff[0] * lu + kap * ((V)s.sa - u0 + u2v));
+        W[1] = v0 - ukc[1] - ht * ((V)s.diff[1] * lv + kap * ((V)s.sb - u2v));
+        Uc[0] = u0;
+        Uc[1] = v0;
+    }
+}
+
+// F~(e) = F(U + e) for the mixed inner loop, written as r + (linear part) e minus
+// h_t times the exact reaction difference, expanded so that no difference of two
+// nearly equal FP32 numbers is formed:
+//   Allen-Cahn:   f(U+e) - f(U) = b (e - 3U^2 e - 3U e^2 - e^3)
+//   Cahn-Hilliard: g(U+e) - g(U) = b (3U^2 e + 3U e^2 + e^3 - e)  (under Lap)
+//   Schnakenberg: (U+e_u)^2 (V+e_v) - U^2 V = 2UV e_u + U^2 e_v + V e_u^2 + 2U e_u e_v + e_u^2 e_v
+// e: accessor of the correction, ub: accessor of the FP32 copy of U.
+template <int EQ, class AccE, class AccU>
+__device__ __forceinline__ void eval_Ftilde(const Slot &s, AccE e, AccU ub, const float *rc, float *W) {
+    const float ht = (float)s.ht, ih2 = (float)s.inv_h2;
+    if constexpr (EQ == EQ_LAP5) {
+        const float e0 = e(0, 0, 0), U = ub(0, 0, 0);
+        const float lap = (e(0, 0, -1) + e(0, 0, 1) + e(0, -1, 0) + e(0, 1, 0) - 4.0f * e0) * ih2;
+        const float df = (float)s.b * (e0 - 3.0f * U * U * e0 - 3.0f * U * e0 * e0 - e0 * e0 * e0);
+        W[0] = rc[0] + e0 - ht * ((float)s.diff[0] * lap + df);
+    } else if constexpr (EQ == EQ_BIH) {
+        const float e0 = e(0, 0, 0);
+        const float el = e(0, 0, -1), er = e(0, 0, 1), eu = e(0, -1, 0), ed = e(0, 1, 0);
+        const float axis1 = el + er + eu + ed;
+        const float diag = e(0, -1, -1) + e(0, -1, 1) + e(0, 1, -1) + e(0, 1, 1);
+        const float axis2 = e(0, 0, -2) + e(0, 0, 2) + e(0, -2, 0) + e(0, 2, 0);
+        const float lap13 = (20.0f * e0 - 8.0f * axis1 + 2.0f * diag + axis2) * (float)s.inv_h4;
+        const float b = (float)s.b;
+        auto dg = [b](float U, float d) { return b * (3.0f * U * U * d + 3.0f * U * d * d + d * d * d - d); };
+        const float lapdg = (dg(ub(0, 0, -1), el) + dg(ub(0, 0, 1), er) + dg(ub(0, -1, 0), eu) +
+                             dg(ub(0, 1, 0), ed) - 4.0f * dg(ub(0, 0, 0), e0)) * ih2;
+        W[0] = rc[0] + e0 + (float)s.diff[0] * ht * lap13 - ht * lapdg;
+    } else {
+        const float eu0 = e(0, 0, 0), ev0 = e(1, 0, 0);
+        const float U = ub(0, 0, 0), Vv = ub(1, 0, 0);
+        const float lu = (e(0, 0, -1) + e(0, 0, 1) + e(0, -1, 0) + e(0, 1, 0) - 4.0f * eu0) * ih2;
+        const float lv = (e(1, 0, -1) + e(1, 0, 1) + e(1, -1, 0) + e(1, 1, 0) - 4.0f * ev0) * ih2;
+        const float d = 2.0f * U * Vv * eu0 + U * U * ev0 + Vv * eu0 * eu0 + 2.0f * U * eu0 * ev0 + eu0 * eu0 * ev0;
+        const float kap = (float)s.kappa;
+        W[0] = rc[0] + eu0 - ht * ((float)s.diff[0] * lu + kap * (-eu0 + d));
+        W[1] = rc[1] + ev0 - ht * ((float)s.diff[1] * lv - kap * d);
+    }
+}
+
+// grad F(U)^T P~ at one point (eq. 23; eq. 32 with the PDE's sign; Sec. 3.4.1).
+// p: accessor of P~; Uc: U at the point per component.
+template <int EQ, typename V, class Acc>
+__device__ __forceinline__ void eval_adjoint(const Slot &s, Acc p, const V *Uc, V *out) {
+    const V ht = (V)s.ht, ih2 = (V)s.inv_h2;
+    if constexpr (EQ == EQ_LAP5) {
+        const V p0 = p(0, 0, 0);
+        const V lap = (p(0, 0, -1) + p(0, 0, 1) + p(0, -1, 0) + p(0, 1, 0) - (V)4 * p0) * ih2;
+        const V U = Uc[0];
+        out[0] = p0 - (V)s.diff[0] * ht * lap - ht * ((V)s.b * ((V)1 - (V)3 * U * U)) * p0;
+    } else if constexpr (EQ == EQ_BIH) {
+        const V p0 = p(0, 0, 0);
+        const V axis1 = p(0, 0, -1) + p(0, 0, 1) + p(0, -1, 0) + p(0, 1, 0);
+        const V diag = p(0, -1, -1) + p(0, -1, 1) + p(0, 1, -1) + p(0, 1, 1);
+        const V axis2 = p(0, 0, -2) + p(0, 0, 2) + p(0, -2, 0) + p(0, 2, 0);
+        const V lap13 = ((V)20 * p0 - (V)8 * axis1 + (V)2 * diag + axis2) * (V)s.inv_h4;
+        const V lap5 = (axis1 - (V)4 * p0) * ih2;
+        const V U = Uc[0];
+        out[0] = p0 + (V)s.diff[0] * ht * lap13 - ht * ((V)s.b * ((V)3 * U * U - (V)1)) * lap5;
+    } else {
+        const V p0 = p(0, 0, 0), q0 = p(1, 0, 0);
+        const V lp = (p(0, 0, -1) + p(0, 0, 1) + p(0, -1, 0) + p(0, 1, 0) - (V)4 * p0) * ih2;
+        const V lq = (p(1, 0, -1) + p(1, 0, 1) + p(1, -1, 0) + p(1, 1, 0) - (V)4 * q0) * ih2;
+        const V U = Uc[0], Vv = Uc[1], kap = (V)s.kappa;
+        out[0] = p0 - ht * ((V)s.diff[0] * lp + kap * (-p0 + (V)2 * U * Vv * (p0 - q0)));
+        out[1] = q0 - ht * ((V)s.diff[1] * lq + kap * U * U * (p0 - q0));
+    }
+}
+
+// ---------------------------------------------------------------- deterministic block sums
+template <int K> __device__ __forceinline__ void block_sum(double *v, double *scratch /* K * NT/64 */) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[k] = x;
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) scratch[k * (NT / 64) + wave] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double x = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) x += scratch[k * (NT / 64) + w];
+        v[k] = x;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool finite_(double x) { return x == x && x - x == 0.0; }
+
+// Slot stop decision after a residual reduction (thread 0 of the last workgroup).
+template <int KIND, int C>
+__device__ __forceinline__ void finalize(const Slot &s, const double *sumsq, const double *mass) {
+    State *st = s.st;
+    double res = 0.0, m = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        res += sqrt(sumsq[c]);
+        m += mass[c];
+    }
+    res /= s.ht;
+    const bool fin = finite_(res);
+    if constexpr (KIND == K_INIT64) {
+        st->iters = 0;
+        st->total_iters = 0;
+        st->outer = 0;
+        st->res = res;
+        st->res0 = res;
+        st->outer_res = res;
+        st->mass = m;
+        int done = 1, status = ST_OK;
+        if (!fin) status = ST_NONFINITE;
+        else if (res <= s.tol) status = ST_OK;
+        else if (s.max_iter <= 0) status = ST_NOCONV;
+        else done = 0;
+        st->status = status;
+        st->done = done;
+        st->outer_done = done;
+    } else if constexpr (KIND == K_ITER64) {
+        const int it = st->iters + 1;
+        st->iters = it;
+        st->total_iters = it;
+        st->res = res;
+        st->outer_res = res;
+        st->mass = m;
+        int done = 1, status = ST_OK;
+        if (!fin || res > GROWTH_LIMIT * st->res0) status = ST_NONFINITE;
+        else if (res <= s.tol) status = ST_OK;
+        else if (it >= s.max_iter) status = ST_NOCONV;
+        else done = 0;
+        st->status = status;
+        st->done = done;
+        st->outer_done = done;
+    } else if constexpr (KIND == K_INNER32) {
+        const int it = st->iters + 1;
+        st->iters = it;
+        st->total_iters = st->total_iters + 1;
+        st->inner_res = res;
+        if (!fin) {
+            st->status = ST_NONFINITE;
+            st->outer_done = 1;
+            st->done = 1;
+        } else if (res <= st->inner_target || it >= s.max_iter) {
+            st->done = 1;
+        }
+    } else {
+        int outer = 0;
+        if constexpr (KIND == K_OUTER_INIT) {
+            st->total_iters = 0;
+            st->res0 = res;
+        } else {
+            outer = st->outer + 1;
+        }
+        st->outer = outer;
+        st->outer_res = res;
+        st->res = res;
+        st->mass = m;
+        int odone = 1, status = ST_OK;
+        if (!fin || res > GROWTH_LIMIT * st->res0) status = ST_NONFINITE;
+        else if (res <= s.tol) status = ST_OK;
+        else if (outer >= s.max_outer) status = ST_NOCONV;
+        else odone = 0;
+        st->status = status;
+        st->outer_done = odone;
+        st->done = odone;
+        st->iters = 0;
+        st->inner_target = s.inner_rtol * res;
+    }
+    st->counter = 0u;
+    __threadfence();
+}
+
+// Write this workgroup's partial sums; the last workgroup of the slot to arrive
+// reduces all of them in block order and runs finalize<KIND>.
+template <int KIND, int C>
+__device__ __forceinline__ void reduce_and_finalize(const Slot &s, double *acc /* 2C */, double *scratch) {
+    __shared__ int am_last;
+    block_sum<2 * C>(acc, scratch);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 2 * C; ++k) s.partials[blockIdx.x * (2 * C) + k] = acc[k];
+        __threadfence();
+        const unsigned prev = atomicAdd(&s.st->counter, 1u);
+        am_last = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!am_last) return;
+    __threadfence();
+    double v[2 * C];
+#pragma unroll
+    for (int k = 0; k < 2 * C; ++k) v[k] = 0.0;
+    for (int bl = threadIdx.x; bl < (int)gridDim.x; bl += NT) {
+#pragma unroll
+        for (int k = 0; k < 2 * C; ++k)
+            v[k] += __hip_atomic_load(&s.partials[bl * (2 * C) + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_sum<2 * C>(v, scratch);
+    if (threadIdx.x == 0) finalize<KIND, C>(s, v, v + C);
+}
+
+// Read the slot state into LDS and decide whether this launch has work.
+template <int KIND> __device__ __forceinline__ bool load_state(const Slot &s, State &sst) {
+    __shared__ int skip;
+    if (threadIdx.x == 0) {
+        sst = *s.st;
+        int sk;
+        if (KIND == K_INIT64 || KIND == K_OUTER_INIT) sk = 0;
+        else if (KIND == K_OUTER_UPD) sk = (sst.outer_done || !sst.done) ? 1 : 0;
+        else sk = sst.done;
+        skip = sk;
+    }
+    __syncthreads();
+    return skip == 0;
+}
+
+// ---------------------------------------------------------------- row pass, forward
+template <typename T, int LOGN, int BC, int EQ, int KIND>
+__global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
+    constexpr int N = 1 << LOGN, H = N / 2;
+    constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
+    constexpr int R = rows_per_block<T, LOGN, C>();
+    constexpr int NREG = C * R / 2;
+    __shared__ cplx<T> buf[C * R * H];
+    __shared__ double scratch[2 * C * (NT / 64)];
+    __shared__ State sst;
+    const Slot &s = *slots[blockIdx.y];
+    if (!load_state<KIND>(s, sst)) return;
+
+    const int y0 = blockIdx.x * R;
+    const size_t NN = (size_t)N * N;
+    const int it = sst.iters;
+    double acc[2 * C];
+#pragma unroll
+    for (int k = 0; k < 2 * C; ++k) acc[k] = 0.0;
+
+    for (int idx = threadIdx.x; idx < R * N; idx += NT) {
+        const int r = idx >> LOGN, x = idx & (N - 1);
+        const int y = y0 + r;
+        const size_t g = (size_t)y * N + x;
+        T wv[C];
+        if constexpr (KIND == K_INIT64 || KIND == K_ITER64) {
+            double W[C], Uc[C], ukc[C];
+            if constexpr (KIND == K_INIT64) {
+                const double *src = s.src;
+                const bool prox = s.init != 0;
+                auto acc_u = [&](int c, int dy, int dx) -> double {
+                    const size_t gi = (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
+                    if (!prox) return src[c * NN + gi];
+                    if constexpr (EQ == EQ_LAP5) return prox_ac(src[gi], s.ht, s.b);
+                    else if constexpr (EQ == EQ_SCHNAK) {
+                        double u, v;
+                        prox_schnak(src[gi], src[NN + gi], s.ht, s.sa, s.sb, s.kappa, u, v);
+                        return c == 0 ? u : v;
+                    } else return src[c * NN + gi];
+                };
+#pragma unroll
+                for (int c = 0; c < C; ++c) ukc[c] = src[c * NN + g];
+                eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
+                double *U0 = (double *)s.U[0];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    U0[c * NN + g] = Uc[c];
+                    s.Uk[c * NN + g] = ukc[c];
+                }
+            } else {
+                const double *Un = (const double *)s.U[(it + 1) & 1];
+                auto acc_u = [&](int c, int dy, int dx) -> double {
+                    return Un[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
+                };
+#pragma unroll
+                for (int c = 0; c < C; ++c) ukc[c] = s.Uk[c * NN + g];
+                eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                acc[c] += W[c] * W[c];
+                acc[C + c] += Uc[c] - ukc[c];
+                wv[c] = (T)W[c];
+            }
+        } else if constexpr (KIND == K_INNER32) {
+            const float *E = (const float *)s.U[(it + 1) & 1];
+            const float *Ub = s.Ub32;
+            auto acc_e = [&](int c, int dy, int dx) -> float {
+                return E[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
+            };
+            auto acc_ub = [&](int c, int dy, int dx) -> float {
+                return Ub[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
+            };
+            float rc[C], W[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) rc[c] = s.r32[c * NN + g];
+            eval_Ftilde<EQ>(s, acc_e, acc_ub, rc, W);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                acc[c] += (double)W[c] * (double)W[c];
+                wv[c] = (T)W[c];
+            }
+        } else {
+            // Mixed outer pass: U_new = U + e (FP64) or the initial U; r = F(U_new) in FP64.
+            double W[C], Uc[C], ukc[C];
+            if constexpr (KIND == K_OUTER_INIT) {
+                const double *src = s.src;
+                const bool prox = s.init != 0;
+                auto acc_u = [&](int c, int dy, int dx) -> double {
+                    const size_t gi = (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
+                    if (!prox) return src[c * NN + gi];
+                    if constexpr (EQ == EQ_LAP5) return prox_ac(src[gi], s.ht, s.b);
+                    else if constexpr (EQ == EQ_SCHNAK) {
+                        double u, v;
+                        prox_schnak(src[gi], src[NN + gi], s.ht, s.sa, s.sb, s.kappa, u, v);
+                        return c == 0 ? u : v;
+                    } else return src[c * NN + gi];
+                };
+#pragma unroll
+                for (int c = 0; c < C; ++c) ukc[c] = src[c * NN + g];
+                eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    s.U64[0][c * NN + g] = Uc[c];
+                    s.Uk[c * NN + g] = ukc[c];
+                }
+            } else {
+                const double *Ucur = s.U64[sst.outer & 1];
+                double *Unext = s.U64[(sst.outer + 1) & 1];
+                const float *E = (const float *)s.U[sst.iters & 1];
+                const bool has_e = sst.iters > 0;
+                auto acc_u = [&](int c, int dy, int dx) -> double {
+                    const size_t gi = c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
+                    return has_e ? Ucur[gi] + (double)E[gi] : Ucur[gi];
+                };
+#pragma unroll
+                for (int c = 0; c < C; ++c) ukc[c] = s.Uk[c * NN + g];
+                eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
+#pragma unroll
+                for (int c = 0; c < C; ++c) Unext[c * NN + g] = Uc[c];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                acc[c] += W[c] * W[c];
+                acc[C + c] += Uc[c] - ukc[c];
+                s.r32[c * NN + g] = (float)W[c];
+                s.Ub32[c * NN + g] = (float)Uc[c];
+                wv[c] = (T)(float)W[c];
+            }
+        }
+        const int pos = (BC == BC_P) ? x : dct_pos(x, N);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T *reg = reinterpret_cast<T *>(buf + (c * R / 2 + r / 2) * N);
+            reg[2 * pos + (r & 1)] = wv[c];
+        }
+    }
+    __syncthreads();
+    const cplx<T> *tw = (const cplx<T> *)s.tw;
+    const cplx<T> *twd = (const cplx<T> *)s.twd;
+    wg_fft<T, LOGN, -1, NREG>(buf, tw);
+    rows_post_forward<T, LOGN, BC, NREG>(buf, twd);
+    // Transposed store: S[c][kx][y0 + r] = buf[c][r][kx]; R consecutive rows per kx.
+    cplx<T> *S = (cplx<T> *)s.S;
+    for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
+        const int r = idx % R, rest = idx / R;
+        const int kx = rest % H, c = rest / H;
+        S[((size_t)c * H + kx) * N + y0 + r] = buf[(c * R + r) * H + kx];
+    }
+    reduce_and_finalize<KIND, C>(s, acc, scratch);
+}
+
+// ---------------------------------------------------------------- column pass
+template <typename T, int LOGN, int BC, int C>
+__global__ __launch_bounds__(NT) void k_cols(Slot *const *slots) {
+    constexpr int N = 1 << LOGN, H = N / 2;
+    constexpr int CB = NT / fft_team<LOGN>();   // column jobs per workgroup
+    __shared__ cplx<T> buf[CB * N];
+    __shared__ State sst;
+    const Slot &s = *slots[blockIdx.y];
+    if (!load_state<K_ITER64>(s, sst)) return;
+    const int njobs_total = C * H;
+    const int job0 = blockIdx.x * CB;
+    const int njobs = min(CB, njobs_total - job0);
+    cplx<T> *S = (cplx<T> *)s.S;
+    for (int idx = threadIdx.x; idx < CB * N; idx += NT) {
+        const int reg = idx >> LOGN, y = idx & (N - 1);
+        if (reg < njobs) {
+            const int pos = (BC == BC_P) ? y : dct_pos(y, N);
+            buf[reg * N + pos] = S[(size_t)(job0 + reg) * N + y];
+        }
+    }
+    __syncthreads();
+    const cplx<T> *tw = (const cplx<T> *)s.tw;
+    const cplx<T> *twd = (const cplx<T> *)s.twd;
+    wg_fft<T, LOGN, -1, CB>(buf, tw);
+    cols_apply_symbol<T, LOGN, BC, CB>(buf, job0, njobs, s, twd);
+    wg_fft<T, LOGN, +1, CB>(buf, tw);
+    for (int idx = threadIdx.x; idx < CB * N; idx += NT) {
+        const int reg = idx >> LOGN, y = idx & (N - 1);
+        if (reg < njobs) {
+            const int pos = (BC == BC_P) ? y : dct_pos(y, N);
+            S[(size_t)(job0 + reg) * N + y] = buf[reg * N + pos];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- row pass, inverse + dual update
+template <typename T, int LOGN, int BC, int C>
+__global__ __launch_bounds__(NT) void k_rowinv(Slot *const *slots) {
+    constexpr int N = 1 << LOGN, H = N / 2;
+    constexpr int R = rows_per_block<T, LOGN, C>();
+    constexpr int NREG = C * R / 2;
+    __shared__ cplx<T> buf[C * R * H];
+    __shared__ State sst;
+    const Slot &s = *slots[blockIdx.y];
+    if (!load_state<K_ITER64>(s, sst)) return;
+    const int y0 = blockIdx.x * R;
+    const size_t NN = (size_t)N * N;
+    const cplx<T> *S = (const cplx<T> *)s.S;
+    for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
+        const int r = idx % R, rest = idx / R;
+        const int kx = rest % H, c = rest / H;
+        buf[(c * R + r) * H + kx] = S[((size_t)c * H + kx) * N + y0 + r];
+    }
+    __syncthreads();
+    const cplx<T> *tw = (const cplx<T> *)s.tw;
+    const cplx<T> *twd = (const cplx<T> *)s.twd;
+    rows_pre_inverse<T, LOGN, BC, NREG>(buf, twd);
+    wg_fft<T, LOGN, +1, NREG>(buf, tw);
+    T *P = (T *)s.P;
+    T *Pt = (T *)s.Pt;
+    const T tp = (T)s.tau_p, om = (T)s.omega;
+    const bool first = sst.iters == 0;
+    for (int idx = threadIdx.x; idx < C * R * N; idx += NT) {
+        const int x = idx & (N - 1), rest = idx >> LOGN;
+        const int r = rest % R, c = rest / R;
+        const int pos = (BC == BC_P) ? x : dct_pos(x, N);
+        const cplx<T> zv = buf[(c * R / 2 + r / 2) * N + pos];
+        const T Y = (r & 1) ? zv.im : zv.re;
+        const size_t g = c * NN + (size_t)(y0 + r) * N + x;
+        const T Pn = first ? (T)0 : P[g];
+        const T Pn1 = Pn + tp * Y;
+        P[g] = Pn1;
+        Pt[g] = Pn1 + om * (Pn1 - Pn);
+    }
+}
+
+// ---------------------------------------------------------------- primal update
+template <typename T, int LOGN, int BC, int EQ, int MODE>
+__global__ __launch_bounds__(NT) void k_upd(Slot *const *slots) {
+    constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
+    constexpr int N = 1 << LOGN;
+    constexpr size_t NN = (size_t)N * N;
+    __shared__ State sst;
+    const Slot &s = *slots[blockIdx.y];
+    if (!load_state<K_ITER64>(s, sst)) return;
+    const size_t g = (size_t)blockIdx.x * NT + threadIdx.x;
+    if (g >= NN) return;
+    const int y = (int)(g >> LOGN), x = (int)(g & (N - 1));
+    const int it = sst.iters;
+    const T *Pt = (const T *)s.Pt;
+    auto acc_p = [&](int c, int dy, int dx) -> T {
+        return Pt[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
+    };
+    T *Unext = (T *)s.U[(it + 1) & 1];
+    const T *Ucur = (const T *)s.U[it & 1];
+    T un[C], Uc[C], adj[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if constexpr (MODE == MODE_F64) {
+            un[c] = Ucur[c * NN + g];
+            Uc[c] = un[c];
+        } else {
+            un[c] = it == 0 ? (T)0 : Ucur[c * NN + g];
+            Uc[c] = s.Ub32[c * NN + g] + un[c];
+        }
+    }
+    eval_adjoint<EQ, T>(s, acc_p, Uc, adj);
+    const T tu = (T)s.tau_u;
+#pragma unroll
+    for (int c = 0; c < C; ++c) Unext[c * NN + g] = un[c] - tu * adj[c];
+}
+
+// ---------------------------------------------------------------- kernel-level entry points
+// W = F(U) in FP64 with per-workgroup squared-norm partials (no transform).
+template <int BC, int EQ>
+__global__ __launch_bounds__(NT) void k_residual(const Slot *sp, const double *U, const double *Uk, double *W,
+                                                 double *partials) {
+    constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
+    __shared__ double scratch[C * (NT / 64)];
+    const Slot &s = *sp;
+    const int N = s.N;
+    const size_t NN = (size_t)N * N;
+    const size_t g = (size_t)blockIdx.x * NT + threadIdx.x;
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0;
+    if (g < NN) {
+        const int y = (int)(g / N), x = (int)(g % N);
+        auto acc_u = [&](int c, int dy, int dx) -> double {
+            return U[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
+        };
+        double ukc[C], Wv[C], Uc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) ukc[c] = Uk[c * NN + g];
+        eval_F<EQ, double>(s, acc_u, ukc, Wv, Uc);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            W[c * NN + g] = Wv[c];
+            acc[c] = Wv[c] * Wv[c];
+        }
+    }
+    block_sum<C>(acc, scratch);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) partials[blockIdx.x * C + c] = acc[c];
+    }
+}
+
+// Pointwise reaction prox of every grid point.
+template <int EQ>
+__global__ __launch_bounds__(NT) void k_prox(const Slot *sp, const double *cin, double *uout) {
+    const Slot &s = *sp;
+    const size_t NN = (size_t)s.N * s.N;
+    const size_t g = (size_t)blockIdx.x * NT + threadIdx.x;
+    if (g >= NN) return;
+    if constexpr (EQ == EQ_LAP5) {
+        uout[g] = prox_ac(cin[g], s.ht, s.b);
+    } else if constexpr (EQ == EQ_SCHNAK) {
+        double u, v;
+        prox_schnak(cin[g], cin[NN + g], s.ht, s.sa, s.sb, s.kappa, u, v);
+        uout[g] = u;
+        uout[NN + g] = v;
+    } else {
+        uout[g] = cin[g];
+    }
+}
+
+// Precondition-only passes (rd_precond_solve): W (FP64) -> row transform -> S,
+// then k_cols, then inverse rows -> Y (FP64).  Use the same transform code as the
+// iteration; the slot's state is not touched.
+template <typename T, int LOGN, int BC, int C>
+__global__ __launch_bounds__(NT) void k_rows_transform_in(Slot *const *slots, const double *W) {
+    constexpr int N = 1 << LOGN, H = N / 2;
+    constexpr int R = rows_per_block<T, LOGN, C>();
+    constexpr int NREG = C * R / 2;
+    __shared__ cplx<T> buf[C * R * H];
+    const Slot &s = *slots[blockIdx.y];
+    const int y0 = blockIdx.x * R;
+    const size_t NN = (size_t)N * N;
+    for (int idx = threadIdx.x; idx < C * R * N; idx += NT) {
+        const int x = idx & (N - 1), rest = idx >> LOGN;
+        const int r = rest % R, c = rest / R;
+        const int pos = (BC == BC_P) ? x : dct_pos(x, N);
+        T *reg = reinterpret_cast<T *>(buf + (c * R / 2 + r / 2) * N);
+        reg[2 * pos + (r & 1)] = (T)W[c * NN + (size_t)(y0 + r) * N + x];
+    }
+    __syncthreads();
+    wg_fft<T, LOGN, -1, NREG>(buf, (const cplx<T> *)s.tw);
+    rows_post_forward<T, LOGN, BC, NREG>(buf, (const cplx<T> *)s.twd);
+    cplx<T> *S = (cplx<T> *)s.S;
+    for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
+        const int r = idx % R, rest = idx / R;
+        const int kx = rest % H, c = rest / H;
+        S[((size_t)c * H + kx) * N + y0 + r] = buf[(c * R + r) * H + kx];
+    }
+}
+
+template <typename T, int LOGN, int BC, int C>
+__global__ __launch_bounds__(NT) void k_rows_transform_out(Slot *const *slots, double *Y) {
+    constexpr int N = 1 << LOGN, H = N / 2;
+    constexpr int R = rows_per_block<T, LOGN, C>();
+    constexpr int NREG = C * R / 2;
+    __shared__ cplx<T> buf[C * R * H];
+    const Slot &s = *slots[blockIdx.y];
+    const int y0 = blockIdx.x * R;
+    const size_t NN = (size_t)N * N;
+    const cplx<T> *S = (const cplx<T> *)s.S;
+    for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
+        const int r = idx % R, rest = idx / R;
+        const int kx = rest % H, c = rest / H;
+        buf[(c * R + r) * H + kx] = S[((size_t)c * H + kx) * N + y0 + r];
+    }
+    __syncthreads();
+    rows_pre_inverse<T, LOGN, BC, NREG>(buf, (const cplx<T> *)s.twd);
+    wg_fft<T, LOGN, +1, NREG>(buf, (const cplx<T> *)s.tw);
+    for (int idx = threadIdx.x; idx < C * R * N; idx += NT) {
+        const int x = idx & (N - 1), rest = idx >> LOGN;
+        const int r = rest % R, c = rest / R;
+        const int pos = (BC == BC_P) ? x : dct_pos(x, N);
+        const cplx<T> zv = buf[(c * R / 2 + r / 2) * N + pos];
+        Y[c * NN + (size_t)(y0 + r) * N + x] = (double)((r & 1) ? zv.im : zv.re);
+    }
+}
+
+}  // namespace rdk

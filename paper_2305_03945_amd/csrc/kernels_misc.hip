@@ -1,0 +1,35 @@
+// The kernel table and the size-independent single-slot kernels (residual and
+// prox) of the kernel-level entry points.
+#include "kernels.h"
+#include "registry.h"
+
+namespace rdk {
+
+KSet g_kernels[2][LOGN_MAX + 1][2][EQ_COUNT];
+
+void launch_residual(int bc, int eq, const Slot *slot_dev, int N, const double *U, const double *Uk, double *W,
+                     double *partials, hipStream_t st) {
+    const int blocks = (int)(((size_t)N * N + NT - 1) / NT);
+    const dim3 g(blocks), b(NT);
+#define RD_RES(BCV, EQV) \
+    hipLaunchKernelGGL((k_residual<BCV, EQV>), g, b, 0, st, slot_dev, U, Uk, W, partials)
+    if (bc == BC_P) {
+        if (eq == EQ_LAP5) RD_RES(BC_P, EQ_LAP5);
+        else if (eq == EQ_BIH) RD_RES(BC_P, EQ_BIH);
+        else RD_RES(BC_P, EQ_SCHNAK);
+    } else {
+        if (eq == EQ_LAP5) RD_RES(BC_N, EQ_LAP5);
+        else if (eq == EQ_BIH) RD_RES(BC_N, EQ_BIH);
+        else RD_RES(BC_N, EQ_SCHNAK);
+    }
+#undef RD_RES
+}
+
+void launch_prox(int eq, const Slot *slot_dev, int N, const double *c, double *u, hipStream_t st) {
+    const int blocks = (int)(((size_t)N * N + NT - 1) / NT);
+    if (eq == EQ_LAP5) hipLaunchKernelGGL((k_prox<EQ_LAP5>), dim3(blocks), dim3(NT), 0, st, slot_dev, c, u);
+    else if (eq == EQ_SCHNAK) hipLaunchKernelGGL((k_prox<EQ_SCHNAK>), dim3(blocks), dim3(NT), 0, st, slot_dev, c, u);
+    else hipLaunchKernelGGL((k_prox<EQ_BIH>), dim3(blocks), dim3(NT), 0, st, slot_dev, c, u);
+}
+
+}  // namespace rdk

@@ -1,0 +1,122 @@
+// Device-side data structures shared by the HIP kernels and the host runtime.
+//
+// A "slot" is one implicit-step problem resident on the GPU: its parameters,
+// its workspace pointers and its iteration state.  Every kernel takes an array
+// of slot pointers and processes slot blockIdx.y, so a single step (rd_step) and
+// a batch of same-shape steps of different trajectories (serving) run the same
+// kernels.  All slots of one launch share N, boundary condition, equation family
+// and precision (these are template parameters); everything else is per slot.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rdk {
+
+// Equation family: fixes the stencil shape and the number of components.
+//   EQ_LAP5   : +lambda Lap (5-point) with the Allen-Cahn reaction (b = 0: heat)
+//   EQ_BIH    : -lambda Lap Lap (13-point) with + Lap g(u) (b = 0: biharmonic)
+//   EQ_SCHNAK : two components, 5-point Laplacians, Schnakenberg kinetics
+enum { EQ_LAP5 = 0, EQ_BIH = 1, EQ_SCHNAK = 2, EQ_COUNT = 3 };
+enum { BC_P = 0, BC_N = 1 };
+// Precision mode of a step: plain FP64 iteration, or FP32 inner iteration on a
+// correction with FP64 outer residual passes.
+enum { MODE_F64 = 0, MODE_MIXED = 1 };
+
+// Step status codes (same values as rd_status).
+enum { ST_OK = 0, ST_NOCONV = -2, ST_NONFINITE = -3 };
+
+constexpr int NT = 256;                 // threads per workgroup, every kernel
+constexpr double GROWTH_LIMIT = 1e8;    // residual growth that counts as divergence
+
+template <typename T> struct cplx { T re, im; };
+
+// Per-slot iteration state, written only by the last workgroup of a
+// residual kernel (fixed-order reduction) and read at the start of every kernel.
+struct State {
+    int done;          // inner loop finished (FP64 path: the whole step)
+    int iters;         // iterations of the current (inner) PDHG loop
+    int total_iters;   // mixed: inner iterations summed over outer passes
+    int outer;         // mixed: outer passes completed
+    int outer_done;    // mixed: step finished
+    int status;        // ST_*
+    unsigned counter;  // arrival counter for the last-block reduction
+    int pad;
+    double res;        // latest ||F/h_t|| of the current loop (FP64 path: paper norm)
+    double res0;       // paper norm at U_0
+    double outer_res;  // mixed: latest FP64 paper norm
+    double inner_target;
+    double mass;       // sum(U - U^k) at the latest FP64 residual evaluation
+    double inner_res;
+};
+
+struct Slot {
+    int N, ncomp, bc, eq;
+    int mode, max_iter, max_outer, init;
+    int nblk_rows, pad0, pad1, pad2;
+    double ht, h, inv_h2, inv_h4;
+    double diff[2];
+    double b;                    // Allen-Cahn / Cahn-Hilliard reaction coefficient
+    double sa, sb, kappa;        // Schnakenberg a, b, kappa
+    double tau_u, tau_p, omega, tol, inner_rtol;
+    double alpha[2], beta[2];    // G = (I - alpha Lap + beta Lap^2)^2 per component
+    // Iterate buffers, element type T of the PDHG loop (double for FP64, float for
+    // the mixed inner loop), each [ncomp][N][N]:
+    void *U[2];                  // FP64: U_n ping-pong; mixed: correction e_n ping-pong
+    void *P, *Pt;                // dual variable and its extrapolation
+    void *S;                     // spectrum, [ncomp][N/2][N] complex, transposed
+    double *Uk;                  // U^k (FP64)
+    double *U64[2];              // mixed: FP64 U ping-pong across outer passes
+    float *r32, *Ub32;           // mixed: FP32 outer residual and FP32 copy of U
+    const double *src;           // caller's u_n
+    double *partials;            // [nblk_rows][2 * ncomp]
+    const double *eig;           // s_k, k < N, for this (N, bc, h)
+    const void *tw;              // exp(-2 pi i k / N), k < N, complex T
+    const void *twd;             // exp(-i pi k / (2N)), k < N, complex T
+    State *st;
+};
+
+// ---------------------------------------------------------------- small helpers
+template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
+    return {a.re + b.re, a.im + b.im};
+}
+template <typename T> __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) {
+    return {a.re - b.re, a.im - b.im};
+}
+template <typename T> __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.re, -a.im}; }
+
+// Ghost-cell index maps.  Periodic: wrap.  Neumann: half-sample mirror
+// (index -1-m -> m, N+m -> N-1-m), valid for offsets up to N.
+template <int BC> __device__ __forceinline__ int wrap(int i, int N) {
+    if (BC == BC_P) return i & (N - 1);
+    if (i < 0) return -1 - i;
+    if (i >= N) return 2 * N - 1 - i;
+    return i;
+}
+
+// Position of x in the Makhoul even/odd reordering used for the DCT-II:
+// x = 2n -> n, x = 2n + 1 -> N - 1 - n.
+__device__ __forceinline__ int dct_pos(int x, int N) { return (x & 1) ? (N - 1 - (x >> 1)) : (x >> 1); }
+
+// Rows of the grid one row-pass workgroup owns: as many as fit ~64 KB of LDS
+// for the transform buffer (ncomp * R * N reals), at least 2 (a row pair), at
+// most 64 and at most N/4 (so that every grid spans at least four workgroups).
+template <typename T, int LOGN, int C> constexpr int rows_per_block() {
+    constexpr int N = 1 << LOGN;
+    constexpr int fit = 65536 / (C * N * (int)sizeof(T));
+    constexpr int cap = N / 4 < 64 ? N / 4 : 64;
+    constexpr int r = fit < 2 ? 2 : (fit > cap ? cap : fit);
+    // round down to a power of two
+    return r >= 64 ? 64 : r >= 32 ? 32 : r >= 16 ? 16 : r >= 8 ? 8 : r >= 4 ? 4 : 2;
+}
+
+// FFT team: threads cooperating on one length-N transform (one radix-8
+// butterfly each); a workgroup runs NT / team transforms side by side.
+template <int LOGN> constexpr int fft_team() {
+    constexpr int n8 = (1 << LOGN) / 8;
+    return n8 < NT ? n8 : NT;
+}
+
+}  // namespace rdk

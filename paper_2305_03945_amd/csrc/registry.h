@@ -1,0 +1,39 @@
+// Host-side table of kernel launchers, one entry per (precision mode, log2 N,
+// boundary condition, equation family).  Each instantiation unit fills the
+// entries of one log2 N; the size-independent kernels fill their own fields.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "rd_dev.h"
+
+namespace rdk {
+
+typedef void (*launch_fn)(Slot *const *slots, int nslots, hipStream_t st);
+typedef void (*launch_io_fn)(Slot *const *slots, int nslots, const double *in, double *out, hipStream_t st);
+
+struct KSet {
+    launch_fn init = nullptr;       // FP64: K_INIT64; mixed: K_OUTER_INIT
+    launch_fn cols = nullptr;       // column pass (T)
+    launch_fn rowinv = nullptr;     // inverse rows + dual update (T)
+    launch_fn upd = nullptr;        // primal update (T)
+    launch_fn rowfwd = nullptr;     // FP64: K_ITER64; mixed: K_INNER32
+    launch_fn outer = nullptr;      // mixed: K_OUTER_UPD
+    launch_io_fn tin = nullptr;     // precond-only: FP64 W -> row transforms into S
+    launch_io_fn tout = nullptr;    // precond-only: S -> inverse rows -> FP64 Y
+    int rows_per_block = 0;
+};
+
+constexpr int LOGN_MIN = 4, LOGN_MAX = 12;
+extern KSet g_kernels[2][LOGN_MAX + 1][2][EQ_COUNT];
+
+void register_upd_kernels();
+#define RD_DECLARE_LOGN(L) void register_logn_##L();
+RD_DECLARE_LOGN(4) RD_DECLARE_LOGN(5) RD_DECLARE_LOGN(6) RD_DECLARE_LOGN(7) RD_DECLARE_LOGN(8)
+RD_DECLARE_LOGN(9) RD_DECLARE_LOGN(10) RD_DECLARE_LOGN(11) RD_DECLARE_LOGN(12)
+#undef RD_DECLARE_LOGN
+
+// Size-independent single-slot kernels used by the kernel-level entry points.
+void launch_residual(int bc, int eq, const Slot *slot_dev, int N, const double *U, const double *Uk, double *W,
+                     double *partials, hipStream_t st);
+void launch_prox(int eq, const Slot *slot_dev, int N, const double *c, double *u, hipStream_t st);
+
+}  // namespace rdk

@@ -1,0 +1,973 @@
+// Host runtime of librdpdhg: argument validation, per-size tables, workspaces,
+// the launch schedule of one implicit step, the kernel-level entry points and
+// the continuous-batching serving loop.  Implements include/rd.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rd.h"
+#include "registry.h"
+
+using namespace rdk;
+
+namespace {
+
+#define RD_CHECK(call)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            if (std::getenv("RD_LOG"))                                                       \
+                std::fprintf(stderr, "[rd] %s:%d %s -> %s\n", __FILE__, __LINE__, #call,   \
+                             hipGetErrorString(e_));                                         \
+            return RD_E_DEVICE;                                                              \
+        }                                                                                    \
+    } while (0)
+
+std::once_flag g_register_once;
+void register_all() {
+    register_logn_4();
+    register_logn_5();
+    register_logn_6();
+    register_logn_7();
+    register_logn_8();
+    register_logn_9();
+    register_logn_10();
+    register_logn_11();
+    register_logn_12();
+}
+
+// ---------------------------------------------------------------- problem description
+struct Desc {
+    int N = 0, logN = 0, C = 1, bc = 0, eq = 0, mode = 0;
+    double h = 0;
+};
+
+int ilog2_exact(int n) {
+    if (n <= 0 || (n & (n - 1))) return -1;
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+rd_status describe(const rd_problem *p, Desc &d) {
+    if (!p) return RD_E_INVALID;
+    if (p->nx != p->ny || !(p->lx > 0.0) || p->lx != p->ly) return RD_E_INVALID;
+    const int l = ilog2_exact(p->nx);
+    if (l < LOGN_MIN || l > LOGN_MAX) return RD_E_INVALID;
+    if (p->bc != RD_BC_PERIODIC && p->bc != RD_BC_NEUMANN) return RD_E_INVALID;
+    d.N = p->nx;
+    d.logN = l;
+    d.bc = p->bc == RD_BC_PERIODIC ? BC_P : BC_N;
+    d.h = p->lx / p->nx;
+    if (p->op == RD_OP_LAP5 && (p->rx == RD_RX_NONE || p->rx == RD_RX_ALLEN_CAHN)) {
+        d.eq = EQ_LAP5;
+        d.C = 1;
+    } else if (p->op == RD_OP_BIHARM13 && (p->rx == RD_RX_NONE || p->rx == RD_RX_CAHN_HILLIARD)) {
+        d.eq = EQ_BIH;
+        d.C = 1;
+    } else if (p->op == RD_OP_LAP5 && p->rx == RD_RX_SCHNAKENBERG) {
+        d.eq = EQ_SCHNAK;
+        d.C = 2;
+    } else {
+        return RD_E_INVALID;
+    }
+    if (!(p->diff[0] >= 0.0) || (d.C == 2 && !(p->diff[1] >= 0.0))) return RD_E_INVALID;
+    return RD_OK;
+}
+
+rd_status check_opts(const rd_opts *o) {
+    if (!o) return RD_E_INVALID;
+    if (!(o->tol >= 0.0) || o->max_iter < 0 || o->max_outer < 0) return RD_E_INVALID;
+    if (!(o->tau_u > 0.0) || !(o->tau_p > 0.0) || !(o->omega >= 0.0)) return RD_E_INVALID;
+    if (o->precision != RD_FP64 && o->precision != RD_FP32_MIXED) return RD_E_INVALID;
+    if (o->init != RD_INIT_PREV && o->init != RD_INIT_PROX) return RD_E_INVALID;
+    if (o->precision == RD_FP32_MIXED && !(o->inner_rtol > 0.0)) return RD_E_INVALID;
+    return RD_OK;
+}
+
+// ---------------------------------------------------------------- per-size tables
+struct Tables {
+    double *eig = nullptr;            // s_k (FP64)
+    void *tw[2] = {nullptr, nullptr};  // [mode]: FFT twiddles in the mode's transform type
+    void *twd[2] = {nullptr, nullptr}; // [mode]: DCT twiddles
+};
+
+// ---------------------------------------------------------------- workspace of one slot
+struct Workspace {
+    int N = 0, C = 0, mode = 0, logN = 0, nblk = 0;
+    size_t bytes = 0;
+    std::vector<void *> allocs;
+    Slot *slot_dev = nullptr;     // device copy of the slot
+    Slot **slot_list_dev = nullptr; // device array {slot_dev}
+    Slot *slot_host = nullptr;    // pinned staging
+    State *st_host = nullptr;     // pinned readback
+    Slot proto{};                 // pointers filled at allocation
+    int last_iters = 0, last_outer = 0, last_inner = 0;
+};
+
+size_t field_bytes(int N, int C, size_t elem) { return (size_t)C * N * N * elem; }
+
+size_t workspace_bytes(int N, int C, int mode, int rows_per_block) {
+    const size_t nblk = rows_per_block > 0 ? (size_t)N / rows_per_block : (size_t)N / 2;
+    size_t b = 0;
+    if (mode == MODE_F64) {
+        b += 5 * field_bytes(N, C, 8);   // U[2], P, Pt, S
+        b += field_bytes(N, C, 8);       // Uk
+    } else {
+        b += 4 * field_bytes(N, C, 4);   // e[2], P, Pt
+        b += field_bytes(N, C, 4);       // S
+        b += 2 * field_bytes(N, C, 4);   // r32, Ub32
+        b += 3 * field_bytes(N, C, 8);   // U64[2], Uk
+    }
+    b += nblk * 2 * C * sizeof(double) + sizeof(State) + sizeof(Slot) + sizeof(Slot *) + 4096;
+    return b;
+}
+
+struct Ticket {
+    rd_info info{};
+    bool done = false;
+};
+
+struct Traj;
+
+struct Ctx {
+    int device = 0;
+    std::map<std::tuple<int, int, uint64_t>, Tables> tables;  // (N, bc, bits of h)
+    std::map<std::tuple<int, int, int>, std::unique_ptr<Workspace>> step_ws;  // (N, C, mode)
+    // scratch for kernel-level entry points
+    Slot *scratch_slot_dev = nullptr;
+    Slot *scratch_slot_host = nullptr;
+    double *scratch_partials = nullptr;
+    size_t scratch_partials_n = 0;
+    std::vector<double> host_partials;
+    // serving
+    size_t budget = 0, resident = 0;
+    uint64_t next_ticket = 1;
+    std::map<uint64_t, Ticket> tickets;
+    std::vector<Traj *> trajs;
+    std::deque<Traj *> admit_queue;
+};
+
+struct PendingStep {
+    uint64_t ticket;
+    double ht;
+};
+
+struct Traj {
+    Ctx *ctx = nullptr;
+    rd_problem prob{};
+    rd_opts opts{};
+    Desc d{};
+    double *u = nullptr;                 // resident state U^k (FP64)
+    std::unique_ptr<Workspace> ws;       // present once admitted
+    std::deque<PendingStep> pending;
+    bool running = false;
+    uint64_t running_ticket = 0;
+    bool queued_for_admission = false;
+};
+
+rd_status dmalloc(Workspace &w, void **p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) return RD_E_NOMEM;
+    w.allocs.push_back(*p);
+    return RD_OK;
+}
+
+void free_workspace(Workspace *w) {
+    if (!w) return;
+    for (void *p : w->allocs) (void)hipFree(p);
+    w->allocs.clear();
+    if (w->slot_host) (void)hipHostFree(w->slot_host);
+    if (w->st_host) (void)hipHostFree(w->st_host);
+    w->slot_host = nullptr;
+    w->st_host = nullptr;
+}
+
+rd_status make_workspace(int N, int logN, int C, int mode, int eq, int bc, std::unique_ptr<Workspace> &out) {
+    auto w = std::make_unique<Workspace>();
+    w->N = N;
+    w->C = C;
+    w->mode = mode;
+    w->logN = logN;
+    const KSet &k = g_kernels[mode][logN][bc][eq];
+    if (!k.init) return RD_E_INVALID;
+    w->nblk = N / k.rows_per_block;
+    w->bytes = workspace_bytes(N, C, mode, k.rows_per_block);
+    Slot &s = w->proto;
+    std::memset(&s, 0, sizeof(Slot));
+    rd_status r;
+    const size_t te = mode == MODE_F64 ? 8 : 4;
+#define ALLOC(ptr, bytes)                                          \
+    do {                                                           \
+        void *p_ = nullptr;                                        \
+        if ((r = dmalloc(*w, &p_, (bytes))) != RD_OK) {            \
+            free_workspace(w.get());                               \
+            return r;                                              \
+        }                                                          \
+        ptr = decltype(ptr)(p_);                                   \
+    } while (0)
+    ALLOC(s.U[0], field_bytes(N, C, te));
+    ALLOC(s.U[1], field_bytes(N, C, te));
+    ALLOC(s.P, field_bytes(N, C, te));
+    ALLOC(s.Pt, field_bytes(N, C, te));
+    ALLOC(s.S, field_bytes(N, C, te));
+    ALLOC(s.Uk, field_bytes(N, C, 8));
+    if (mode == MODE_MIXED) {
+        ALLOC(s.U64[0], field_bytes(N, C, 8));
+        ALLOC(s.U64[1], field_bytes(N, C, 8));
+        ALLOC(s.r32, field_bytes(N, C, 4));
+        ALLOC(s.Ub32, field_bytes(N, C, 4));
+    }
+    ALLOC(s.partials, (size_t)w->nblk * 2 * C * sizeof(double));
+    ALLOC(s.st, sizeof(State));
+    ALLOC(w->slot_dev, sizeof(Slot));
+    ALLOC(w->slot_list_dev, sizeof(Slot *));
+#undef ALLOC
+    if (hipHostMalloc((void **)&w->slot_host, sizeof(Slot), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&w->st_host, sizeof(State), hipHostMallocDefault) != hipSuccess) {
+        free_workspace(w.get());
+        return RD_E_NOMEM;
+    }
+    if (hipMemset(s.st, 0, sizeof(State)) != hipSuccess ||
+        hipMemcpy(w->slot_list_dev, &w->slot_dev, sizeof(Slot *), hipMemcpyHostToDevice) != hipSuccess) {
+        free_workspace(w.get());
+        return RD_E_DEVICE;
+    }
+    out = std::move(w);
+    return RD_OK;
+}
+
+void fill_tables_host(int N, int bc, double h, std::vector<double> &eig, std::vector<double> &tw,
+                      std::vector<double> &twd) {
+    eig.resize(N);
+    tw.resize(2 * N);
+    twd.resize(2 * N);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < N; ++k) {
+        const long double arg = (bc == BC_P) ? pi * k / N : pi * k / (2.0L * N);
+        const long double sn = std::sin(arg);
+        eig[k] = (double)(4.0L / ((long double)h * h) * sn * sn);
+        const long double a = 2.0L * pi * k / N;
+        tw[2 * k] = (double)std::cos(a);
+        tw[2 * k + 1] = (double)(-std::sin(a));
+        const long double b = pi * k / (2.0L * N);
+        twd[2 * k] = (double)std::cos(b);
+        twd[2 * k + 1] = (double)(-std::sin(b));
+    }
+}
+
+rd_status get_tables(Ctx *c, int N, int bc, double h, Tables *&out) {
+    uint64_t hb;
+    std::memcpy(&hb, &h, sizeof(hb));
+    auto key = std::make_tuple(N, bc, hb);
+    auto it = c->tables.find(key);
+    if (it != c->tables.end()) {
+        out = &it->second;
+        return RD_OK;
+    }
+    std::vector<double> eig, tw, twd;
+    fill_tables_host(N, bc, h, eig, tw, twd);
+    std::vector<float> tw32(tw.begin(), tw.end()), twd32(twd.begin(), twd.end());
+    Tables t;
+    RD_CHECK(hipMalloc((void **)&t.eig, N * sizeof(double)));
+    RD_CHECK(hipMalloc(&t.tw[0], 2 * N * sizeof(double)));
+    RD_CHECK(hipMalloc(&t.twd[0], 2 * N * sizeof(double)));
+    RD_CHECK(hipMalloc(&t.tw[1], 2 * N * sizeof(float)));
+    RD_CHECK(hipMalloc(&t.twd[1], 2 * N * sizeof(float)));
+    RD_CHECK(hipMemcpy(t.eig, eig.data(), N * sizeof(double), hipMemcpyHostToDevice));
+    RD_CHECK(hipMemcpy(t.tw[0], tw.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice));
+    RD_CHECK(hipMemcpy(t.twd[0], twd.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice));
+    RD_CHECK(hipMemcpy(t.tw[1], tw32.data(), 2 * N * sizeof(float), hipMemcpyHostToDevice));
+    RD_CHECK(hipMemcpy(t.twd[1], twd32.data(), 2 * N * sizeof(float), hipMemcpyHostToDevice));
+    out = &(c->tables[key] = t);
+    return RD_OK;
+}
+
+// Fill the parameter part of a slot from the problem and options.
+void fill_params(Slot &s, const rd_problem *p, const rd_opts *o, const Desc &d, double ht) {
+    s.N = d.N;
+    s.ncomp = d.C;
+    s.bc = d.bc;
+    s.eq = d.eq;
+    s.mode = o ? (o->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64) : MODE_F64;
+    s.max_iter = o ? o->max_iter : 0;
+    s.max_outer = o ? o->max_outer : 0;
+    s.init = o ? o->init : 0;
+    s.ht = ht;
+    s.h = d.h;
+    s.inv_h2 = 1.0 / (d.h * d.h);
+    s.inv_h4 = s.inv_h2 * s.inv_h2;
+    s.diff[0] = p->diff[0];
+    s.diff[1] = d.C == 2 ? p->diff[1] : 0.0;
+    s.b = 0.0;
+    s.sa = s.sb = 0.0;
+    s.kappa = 0.0;
+    if (p->rx == RD_RX_ALLEN_CAHN || p->rx == RD_RX_CAHN_HILLIARD) s.b = p->p[0];
+    if (p->rx == RD_RX_SCHNAKENBERG) {
+        s.sa = p->p[0];
+        s.sb = p->p[1];
+        s.kappa = p->p[2];
+    }
+    if (o) {
+        s.tau_u = o->tau_u;
+        s.tau_p = o->tau_p;
+        s.omega = o->omega;
+        s.tol = o->tol;
+        s.inner_rtol = o->inner_rtol;
+    }
+    // G = (I - alpha Lap + beta Lap^2)^2 per component
+    for (int c = 0; c < 2; ++c) {
+        s.alpha[c] = 0.0;
+        s.beta[c] = 0.0;
+    }
+    if (d.eq == EQ_LAP5) s.alpha[0] = p->diff[0] * ht;
+    else if (d.eq == EQ_BIH) s.beta[0] = p->diff[0] * ht;
+    else {
+        s.alpha[0] = p->diff[0] * ht;
+        s.alpha[1] = p->diff[1] * ht;
+    }
+}
+
+void bind_workspace(Slot &s, const Workspace &w, const Tables &t) {
+    const Slot &q = w.proto;
+    for (int i = 0; i < 2; ++i) {
+        s.U[i] = q.U[i];
+        s.U64[i] = q.U64[i];
+    }
+    s.P = q.P;
+    s.Pt = q.Pt;
+    s.S = q.S;
+    s.Uk = q.Uk;
+    s.r32 = q.r32;
+    s.Ub32 = q.Ub32;
+    s.partials = q.partials;
+    s.st = q.st;
+    s.nblk_rows = w.nblk;
+    s.eig = t.eig;
+    s.tw = t.tw[w.mode];
+    s.twd = t.twd[w.mode];
+}
+
+// Launch schedule of one step, or of a batch of running slots of one key.
+// `slots`: device array of nslots Slot pointers.  Each call enqueues `iters`
+// PDHG iterations (FP64), or `passes` rounds of `iters` inner iterations each
+// followed by an outer FP64 pass (mixed).  Finished slots turn them into no-ops.
+void enqueue_round(const KSet &k, int mode, Slot *const *slots, int nslots, int iters, int passes, hipStream_t st) {
+    if (mode == MODE_F64) {
+        for (int i = 0; i < iters; ++i) {
+            k.cols(slots, nslots, st);
+            k.rowinv(slots, nslots, st);
+            k.upd(slots, nslots, st);
+            k.rowfwd(slots, nslots, st);
+        }
+    } else {
+        for (int p = 0; p < passes; ++p) {
+            for (int i = 0; i < iters; ++i) {
+                k.cols(slots, nslots, st);
+                k.rowinv(slots, nslots, st);
+                k.upd(slots, nslots, st);
+                k.rowfwd(slots, nslots, st);
+            }
+            k.outer(slots, nslots, st);
+        }
+    }
+}
+
+void info_from_state(const State &s, int mode, rd_info *info) {
+    if (!info) return;
+    std::memset(info, 0, sizeof(*info));
+    info->iters = mode == MODE_F64 ? s.iters : s.total_iters;
+    info->outer = mode == MODE_F64 ? 0 : s.outer;
+    info->residual_l2 = mode == MODE_F64 ? s.res : s.outer_res;
+    info->residual0 = s.res0;
+    info->mass_drift = s.mass;
+    info->status = s.status;
+}
+
+const void *final_buffer(const Workspace &w, const State &s) {
+    if (w.mode == MODE_F64) return w.proto.U[s.iters & 1];
+    return w.proto.U64[s.outer & 1];
+}
+
+rd_status get_step_workspace(Ctx *c, const Desc &d, int mode, Workspace *&out) {
+    auto key = std::make_tuple(d.N, d.C, mode);
+    auto it = c->step_ws.find(key);
+    if (it != c->step_ws.end()) {
+        // a workspace is reusable across equations of the same shape; the
+        // row-block count depends only on (N, C, mode)
+        out = it->second.get();
+        return RD_OK;
+    }
+    std::unique_ptr<Workspace> w;
+    rd_status r = make_workspace(d.N, d.logN, d.C, mode, d.eq, d.bc, w);
+    if (r != RD_OK) return r;
+    out = w.get();
+    c->step_ws[key] = std::move(w);
+    return RD_OK;
+}
+
+// Run one step to completion on the workspace's single slot.
+rd_status run_step(Ctx *c, Workspace &w, const KSet &k, hipStream_t st, int max_iter, int max_outer) {
+    Slot *const *slots = w.slot_list_dev;
+    k.init(slots, 1, st);
+    RD_CHECK(hipGetLastError());
+    int issued = 0, rounds = 0;
+    while (true) {
+        int iters, passes = 1;
+        if (w.mode == MODE_F64) {
+            iters = rounds == 0 ? (w.last_iters > 0 ? w.last_iters + 1 : 8) : std::max(4, issued / 4);
+            if (max_iter - issued + 1 < iters) iters = std::max(1, max_iter - issued + 1);
+        } else {
+            iters = rounds == 0 ? (w.last_inner > 0 ? w.last_inner + 1 : 6) : std::max(3, w.last_inner);
+            passes = rounds == 0 ? (w.last_outer > 0 ? w.last_outer : 3) : 1;
+        }
+        enqueue_round(k, w.mode, slots, 1, iters, passes, st);
+        RD_CHECK(hipGetLastError());
+        issued += iters * passes;
+        ++rounds;
+        RD_CHECK(hipMemcpyAsync(w.st_host, w.proto.st, sizeof(State), hipMemcpyDeviceToHost, st));
+        RD_CHECK(hipStreamSynchronize(st));
+        const State &s = *w.st_host;
+        const bool finished = w.mode == MODE_F64 ? s.done != 0 : s.outer_done != 0;
+        if (finished) break;
+        // The device enforces max_iter / max_outer; this bound only guards
+        // against a host-side schedule that never reaches them.
+        const long cap = w.mode == MODE_F64 ? (long)max_iter + 8
+                                            : (long)(max_outer + 1) * (long)(max_iter + 1) + 16;
+        if (issued > cap + 64) return RD_E_DEVICE;
+    }
+    const State &s = *w.st_host;
+    if (w.mode == MODE_F64) {
+        w.last_iters = s.iters;
+    } else {
+        w.last_outer = std::max(1, s.outer);
+        w.last_inner = s.outer > 0 ? std::max(1, (s.total_iters + s.outer - 1) / s.outer) : 6;
+    }
+    (void)c;
+    return RD_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *rd_status_str(rd_status s) {
+    switch (s) {
+    case RD_OK: return "ok";
+    case RD_E_INVALID: return "invalid argument";
+    case RD_E_NOCONV: return "iteration limit reached";
+    case RD_E_NONFINITE: return "residual non-finite or diverging";
+    case RD_E_NOMEM: return "out of device memory or budget";
+    case RD_E_DEVICE: return "HIP runtime error";
+    case RD_E_BUSY: return "not finished";
+    }
+    return "unknown status";
+}
+
+void rd_default_opts(rd_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-10;
+    o->max_iter = 10000;
+    o->max_outer = 20;
+    o->tau_u = 0.9;
+    o->tau_p = 0.9;
+    o->omega = 1.0;
+    o->precision = RD_FP64;
+    o->init = RD_INIT_PREV;
+    o->inner_rtol = 1e-3;
+}
+
+rd_status rd_create(int device, void **out) {
+    if (!out) return RD_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    RD_CHECK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return RD_E_INVALID;
+    RD_CHECK(hipSetDevice(device));
+    std::call_once(g_register_once, register_all);
+    auto *c = new Ctx();
+    c->device = device;
+    if (hipMalloc((void **)&c->scratch_slot_dev, sizeof(Slot)) != hipSuccess ||
+        hipHostMalloc((void **)&c->scratch_slot_host, sizeof(Slot), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return RD_E_NOMEM;
+    }
+    *out = c;
+    return RD_OK;
+}
+
+rd_status rd_destroy(void *ctx) {
+    if (!ctx) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (Traj *t : c->trajs) {
+        if (t->ws) free_workspace(t->ws.get());
+        if (t->u) (void)hipFree(t->u);
+        delete t;
+    }
+    for (auto &kv : c->step_ws) free_workspace(kv.second.get());
+    for (auto &kv : c->tables) {
+        (void)hipFree(kv.second.eig);
+        for (int i = 0; i < 2; ++i) {
+            (void)hipFree(kv.second.tw[i]);
+            (void)hipFree(kv.second.twd[i]);
+        }
+    }
+    if (c->scratch_slot_dev) (void)hipFree(c->scratch_slot_dev);
+    if (c->scratch_slot_host) (void)hipHostFree(c->scratch_slot_host);
+    if (c->scratch_partials) (void)hipFree(c->scratch_partials);
+    delete c;
+    return RD_OK;
+}
+
+size_t rd_footprint_bytes(const rd_problem *prob, const rd_opts *opts) {
+    Desc d;
+    if (describe(prob, d) != RD_OK || check_opts(opts) != RD_OK) return 0;
+    std::call_once(g_register_once, register_all);
+    const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
+    const int rpb = g_kernels[mode][d.logN][d.bc][d.eq].rows_per_block;
+    // resident trajectory state + the step workspace
+    return workspace_bytes(d.N, d.C, mode, rpb) + field_bytes(d.N, d.C, 8);
+}
+
+rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t, const double *u_n,
+                  double *u_np1, void *hip_stream, rd_info *info) {
+    if (!ctx || !u_n || !u_np1) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    Desc d;
+    rd_status r = describe(prob, d);
+    if (r != RD_OK) return r;
+    if ((r = check_opts(opts)) != RD_OK) return r;
+    if (!(h_t > 0.0) || !std::isfinite(h_t)) return RD_E_INVALID;
+    RD_CHECK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
+    const KSet &k = g_kernels[mode][d.logN][d.bc][d.eq];
+    Tables *t = nullptr;
+    if ((r = get_tables(c, d.N, d.bc, d.h, t)) != RD_OK) return r;
+    Workspace *w = nullptr;
+    if ((r = get_step_workspace(c, d, mode, w)) != RD_OK) return r;
+    Slot &s = *w->slot_host;
+    std::memset(&s, 0, sizeof(Slot));
+    fill_params(s, prob, opts, d, h_t);
+    bind_workspace(s, *w, *t);
+    s.src = u_n;
+    RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
+    if ((r = run_step(c, *w, k, st, opts->max_iter, opts->max_outer)) != RD_OK) return r;
+    const State &sf = *w->st_host;
+    RD_CHECK(hipMemcpyAsync(u_np1, final_buffer(*w, sf), field_bytes(d.N, d.C, 8), hipMemcpyDeviceToDevice, st));
+    RD_CHECK(hipStreamSynchronize(st));
+    info_from_state(sf, mode, info);
+    return (rd_status)sf.status;
+}
+
+rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
+                               const double *u_n, int32_t reps, void *hip_stream, double *ms_out) {
+    if (!ctx || !u_n || !ms_out || reps <= 0) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    Desc d;
+    rd_status r = describe(prob, d);
+    if (r != RD_OK) return r;
+    if ((r = check_opts(opts)) != RD_OK) return r;
+    if (!(h_t > 0.0)) return RD_E_INVALID;
+    RD_CHECK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
+    const KSet &k = g_kernels[mode][d.logN][d.bc][d.eq];
+    Tables *t = nullptr;
+    if ((r = get_tables(c, d.N, d.bc, d.h, t)) != RD_OK) return r;
+    Workspace *w = nullptr;
+    if ((r = get_step_workspace(c, d, mode, w)) != RD_OK) return r;
+    Slot &s = *w->slot_host;
+    std::memset(&s, 0, sizeof(Slot));
+    fill_params(s, prob, opts, d, h_t);
+    bind_workspace(s, *w, *t);
+    s.src = u_n;
+    s.max_iter = 1 << 30;   // the stop decision must not end the timed launches
+    s.tol = 0.0;
+    RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
+    k.init(w->slot_list_dev, 1, st);
+    RD_CHECK(hipGetLastError());
+    RD_CHECK(hipStreamSynchronize(st));
+    // State that every kernel treats as "iteration 1 of a running step".
+    State run{};
+    RD_CHECK(hipMemcpy(&run, w->proto.st, sizeof(State), hipMemcpyDeviceToHost));
+    run.done = 0;
+    run.outer_done = 0;
+    run.iters = 1;
+    run.counter = 0;
+    if (run.res0 == 0.0) run.res0 = 1.0;
+    *w->st_host = run;
+    launch_fn fns[4] = {k.cols, k.rowinv, k.upd, k.rowfwd};
+    std::vector<hipEvent_t> ev(2 * (size_t)reps);
+    for (auto &e : ev) RD_CHECK(hipEventCreate(&e));
+    for (int kk = 0; kk < 4; ++kk) {
+        for (int i = 0; i < reps; ++i) {
+            RD_CHECK(hipMemcpyAsync(w->proto.st, w->st_host, sizeof(State), hipMemcpyHostToDevice, st));
+            RD_CHECK(hipEventRecord(ev[2 * i], st));
+            fns[kk](w->slot_list_dev, 1, st);
+            RD_CHECK(hipEventRecord(ev[2 * i + 1], st));
+        }
+        RD_CHECK(hipGetLastError());
+        RD_CHECK(hipStreamSynchronize(st));
+        double tot = 0.0;
+        for (int i = 0; i < reps; ++i) {
+            float ms = 0.f;
+            RD_CHECK(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+            tot += ms;
+        }
+        ms_out[kk] = tot / reps;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    return RD_OK;
+}
+
+// ---------------------------------------------------------------- kernel-level entry points
+rd_status rd_residual(void *ctx, const rd_problem *prob, double h_t, const double *u, const double *uk, double *w,
+                      void *hip_stream, double *res_l2) {
+    if (!ctx || !u || !uk || !w) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    Desc d;
+    rd_status r = describe(prob, d);
+    if (r != RD_OK) return r;
+    if (!(h_t > 0.0)) return RD_E_INVALID;
+    RD_CHECK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    Slot &s = *c->scratch_slot_host;
+    std::memset(&s, 0, sizeof(Slot));
+    fill_params(s, prob, nullptr, d, h_t);
+    const size_t blocks = ((size_t)d.N * d.N + NT - 1) / NT;
+    const size_t need = blocks * d.C;
+    if (c->scratch_partials_n < need) {
+        if (c->scratch_partials) (void)hipFree(c->scratch_partials);
+        c->scratch_partials = nullptr;
+        c->scratch_partials_n = 0;
+        RD_CHECK(hipMalloc((void **)&c->scratch_partials, need * sizeof(double)));
+        c->scratch_partials_n = need;
+    }
+    RD_CHECK(hipMemcpyAsync(c->scratch_slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
+    launch_residual(d.bc, d.eq, c->scratch_slot_dev, d.N, u, uk, w, c->scratch_partials, st);
+    RD_CHECK(hipGetLastError());
+    c->host_partials.resize(need);
+    RD_CHECK(hipMemcpyAsync(c->host_partials.data(), c->scratch_partials, need * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
+    RD_CHECK(hipStreamSynchronize(st));
+    if (res_l2) {
+        double res = 0.0;
+        for (int comp = 0; comp < d.C; ++comp) {
+            double acc = 0.0;
+            for (size_t b = 0; b < blocks; ++b) acc += c->host_partials[b * d.C + comp];
+            res += std::sqrt(acc);
+        }
+        *res_l2 = res / h_t;
+    }
+    return RD_OK;
+}
+
+rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_t precision, const double *w_in,
+                           double *y, void *hip_stream) {
+    if (!ctx || !w_in || !y) return RD_E_INVALID;
+    if (precision != RD_FP64 && precision != RD_FP32_MIXED) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    Desc d;
+    rd_status r = describe(prob, d);
+    if (r != RD_OK) return r;
+    if (!(h_t > 0.0)) return RD_E_INVALID;
+    RD_CHECK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int mode = precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
+    const KSet &k = g_kernels[mode][d.logN][d.bc][d.eq];
+    Tables *t = nullptr;
+    if ((r = get_tables(c, d.N, d.bc, d.h, t)) != RD_OK) return r;
+    Workspace *w = nullptr;
+    if ((r = get_step_workspace(c, d, mode, w)) != RD_OK) return r;
+    Slot &s = *w->slot_host;
+    std::memset(&s, 0, sizeof(Slot));
+    fill_params(s, prob, nullptr, d, h_t);
+    bind_workspace(s, *w, *t);
+    RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
+    RD_CHECK(hipMemsetAsync(w->proto.st, 0, sizeof(State), st));   // done = 0: column pass active
+    k.tin(w->slot_list_dev, 1, w_in, nullptr, st);
+    k.cols(w->slot_list_dev, 1, st);
+    k.tout(w->slot_list_dev, 1, nullptr, y, st);
+    RD_CHECK(hipGetLastError());
+    RD_CHECK(hipStreamSynchronize(st));
+    return RD_OK;
+}
+
+rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *cin, double *u, void *hip_stream) {
+    if (!ctx || !cin || !u) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    Desc d;
+    rd_status r = describe(prob, d);
+    if (r != RD_OK) return r;
+    if (!(h_t > 0.0)) return RD_E_INVALID;
+    RD_CHECK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    Slot &s = *c->scratch_slot_host;
+    std::memset(&s, 0, sizeof(Slot));
+    fill_params(s, prob, nullptr, d, h_t);
+    RD_CHECK(hipMemcpyAsync(c->scratch_slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
+    launch_prox(d.eq, c->scratch_slot_dev, d.N, cin, u, st);
+    RD_CHECK(hipGetLastError());
+    RD_CHECK(hipStreamSynchronize(st));
+    return RD_OK;
+}
+
+// ---------------------------------------------------------------- serving
+rd_status rd_serve_set_budget(void *ctx, size_t bytes) {
+    if (!ctx) return RD_E_INVALID;
+    ((Ctx *)ctx)->budget = bytes;
+    return RD_OK;
+}
+
+rd_status rd_traj_open(void *ctx, const rd_problem *prob, const rd_opts *opts, const double *u0, void *hip_stream,
+                       void **out) {
+    if (!ctx || !u0 || !out) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    Desc d;
+    rd_status r = describe(prob, d);
+    if (r != RD_OK) return r;
+    if ((r = check_opts(opts)) != RD_OK) return r;
+    RD_CHECK(hipSetDevice(c->device));
+    auto *t = new Traj();
+    t->ctx = c;
+    t->prob = *prob;
+    t->opts = *opts;
+    t->d = d;
+    t->d.mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
+    const size_t fb = field_bytes(d.N, d.C, 8);
+    if (hipMalloc((void **)&t->u, fb) != hipSuccess) {
+        delete t;
+        return RD_E_NOMEM;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (hipMemcpyAsync(t->u, u0, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipFree(t->u);
+        delete t;
+        return RD_E_DEVICE;
+    }
+    c->trajs.push_back(t);
+    *out = t;
+    return RD_OK;
+}
+
+rd_status rd_traj_submit(void *traj, double h_t, uint64_t *ticket) {
+    if (!traj || !ticket || !(h_t > 0.0) || !std::isfinite(h_t)) return RD_E_INVALID;
+    Traj *t = (Traj *)traj;
+    Ctx *c = t->ctx;
+    const uint64_t id = c->next_ticket++;
+    c->tickets[id] = Ticket{};
+    t->pending.push_back(PendingStep{id, h_t});
+    if (!t->ws && !t->queued_for_admission) {
+        c->admit_queue.push_back(t);
+        t->queued_for_admission = true;
+    }
+    *ticket = id;
+    return RD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Serving: one pump round.
+//  1. Admit queued trajectories in arrival order while the resident budget allows.
+//  2. Start the next pending step of every admitted idle trajectory (batched init
+//     launch per key).
+//  3. Advance every running slot by one round of iterations, batched per key
+//     (N, bc, equation family, precision): one launch per kernel for all of them.
+//  4. Read back the states, retire finished steps: copy U^{k+1} to the resident
+//     state, record the ticket's info.
+struct GroupKey {
+    int mode, logN, bc, eq;
+    bool operator<(const GroupKey &o) const {
+        return std::tie(mode, logN, bc, eq) < std::tie(o.mode, o.logN, o.bc, o.eq);
+    }
+};
+
+struct BatchBuffers {
+    Slot **dev = nullptr;
+    Slot **host = nullptr;
+    int cap = 0;
+};
+std::map<Ctx *, std::map<GroupKey, BatchBuffers>> g_batch;
+
+rd_status batch_list(Ctx *c, const GroupKey &key, const std::vector<Traj *> &ts, Slot **&dev, hipStream_t st) {
+    BatchBuffers &b = g_batch[c][key];
+    const int n = (int)ts.size();
+    if (b.cap < n) {
+        if (b.dev) (void)hipFree(b.dev);
+        if (b.host) (void)hipHostFree(b.host);
+        b.dev = nullptr;
+        b.host = nullptr;
+        b.cap = 0;
+        const int cap = std::max(16, 2 * n);
+        RD_CHECK(hipMalloc((void **)&b.dev, cap * sizeof(Slot *)));
+        RD_CHECK(hipHostMalloc((void **)&b.host, cap * sizeof(Slot *), hipHostMallocDefault));
+        b.cap = cap;
+    }
+    for (int i = 0; i < n; ++i) b.host[i] = ts[i]->ws->slot_dev;
+    RD_CHECK(hipMemcpyAsync(b.dev, b.host, n * sizeof(Slot *), hipMemcpyHostToDevice, st));
+    dev = b.dev;
+    return RD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
+    (void)max_wait_us;
+    if (!ctx) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    RD_CHECK(hipSetDevice(c->device));
+    hipStream_t st = nullptr;
+    rd_status r;
+    // 1. admission
+    while (!c->admit_queue.empty()) {
+        Traj *t = c->admit_queue.front();
+        const size_t need = workspace_bytes(t->d.N, t->d.C, t->d.mode,
+                                            g_kernels[t->d.mode][t->d.logN][t->d.bc][t->d.eq].rows_per_block);
+        if (c->budget && c->resident + need > c->budget && c->resident > 0) break;
+        std::unique_ptr<Workspace> w;
+        r = make_workspace(t->d.N, t->d.logN, t->d.C, t->d.mode, t->d.eq, t->d.bc, w);
+        if (r == RD_E_NOMEM && c->resident > 0) break;
+        if (r != RD_OK) return r;
+        t->ws = std::move(w);
+        c->resident += need;
+        c->admit_queue.pop_front();
+        t->queued_for_admission = false;
+    }
+    // 2. start pending steps, 3. advance, per key
+    std::map<GroupKey, std::vector<Traj *>> starting, running;
+    for (Traj *t : c->trajs) {
+        if (!t->ws) continue;
+        GroupKey key{t->d.mode, t->d.logN, t->d.bc, t->d.eq};
+        if (!t->running && !t->pending.empty()) {
+            PendingStep ps = t->pending.front();
+            t->pending.pop_front();
+            Tables *tb = nullptr;
+            if ((r = get_tables(c, t->d.N, t->d.bc, t->d.h, tb)) != RD_OK) return r;
+            Slot &s = *t->ws->slot_host;
+            std::memset(&s, 0, sizeof(Slot));
+            fill_params(s, &t->prob, &t->opts, t->d, ps.ht);
+            bind_workspace(s, *t->ws, *tb);
+            s.src = t->u;
+            RD_CHECK(hipMemcpyAsync(t->ws->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
+            t->running = true;
+            t->running_ticket = ps.ticket;
+            starting[key].push_back(t);
+        }
+        if (t->running) running[key].push_back(t);
+    }
+    for (auto &kv : starting) {
+        Slot **dev = nullptr;
+        if ((r = batch_list(c, kv.first, kv.second, dev, st)) != RD_OK) return r;
+        g_kernels[kv.first.mode][kv.first.logN][kv.first.bc][kv.first.eq].init(dev, (int)kv.second.size(), st);
+        RD_CHECK(hipGetLastError());
+        // the list buffer is reused below: wait for the init launch to consume it
+        RD_CHECK(hipStreamSynchronize(st));
+    }
+    for (auto &kv : running) {
+        const GroupKey &key = kv.first;
+        Slot **dev = nullptr;
+        if ((r = batch_list(c, key, kv.second, dev, st)) != RD_OK) return r;
+        int iters = 0;
+        for (Traj *t : kv.second) {
+            const Workspace &w = *t->ws;
+            iters = std::max(iters, key.mode == MODE_F64 ? (w.last_iters > 0 ? w.last_iters + 1 : 8)
+                                                         : (w.last_inner > 0 ? w.last_inner + 1 : 6));
+        }
+        iters = std::min(iters, 64);
+        enqueue_round(g_kernels[key.mode][key.logN][key.bc][key.eq], key.mode, dev, (int)kv.second.size(), iters, 1,
+                      st);
+        RD_CHECK(hipGetLastError());
+        for (Traj *t : kv.second)
+            RD_CHECK(hipMemcpyAsync(t->ws->st_host, t->ws->proto.st, sizeof(State), hipMemcpyDeviceToHost, st));
+        RD_CHECK(hipStreamSynchronize(st));
+    }
+    // 4. retire
+    for (auto &kv : running) {
+        for (Traj *t : kv.second) {
+            Workspace &w = *t->ws;
+            const State &s = *w.st_host;
+            const bool fin = w.mode == MODE_F64 ? s.done != 0 : s.outer_done != 0;
+            if (!fin) continue;
+            RD_CHECK(hipMemcpyAsync(t->u, final_buffer(w, s), field_bytes(t->d.N, t->d.C, 8),
+                                    hipMemcpyDeviceToDevice, st));
+            Ticket &tk = c->tickets[t->running_ticket];
+            info_from_state(s, w.mode, &tk.info);
+            tk.done = true;
+            if (w.mode == MODE_F64) w.last_iters = s.iters;
+            else {
+                w.last_outer = std::max(1, s.outer);
+                w.last_inner = s.outer > 0 ? std::max(1, (s.total_iters + s.outer - 1) / s.outer) : 6;
+            }
+            t->running = false;
+        }
+    }
+    RD_CHECK(hipStreamSynchronize(st));
+    return RD_OK;
+}
+
+rd_status rd_poll(void *ctx, uint64_t ticket, rd_info *info) {
+    if (!ctx) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    auto it = c->tickets.find(ticket);
+    if (it == c->tickets.end()) return RD_E_INVALID;
+    if (!it->second.done) return RD_E_BUSY;
+    if (info) *info = it->second.info;
+    return (rd_status)it->second.info.status;
+}
+
+rd_status rd_traj_read(void *traj, double *u_out, void *hip_stream) {
+    if (!traj || !u_out) return RD_E_INVALID;
+    Traj *t = (Traj *)traj;
+    RD_CHECK(hipSetDevice(t->ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    RD_CHECK(hipMemcpyAsync(u_out, t->u, field_bytes(t->d.N, t->d.C, 8), hipMemcpyDeviceToDevice, st));
+    RD_CHECK(hipStreamSynchronize(st));
+    return RD_OK;
+}
+
+rd_status rd_traj_close(void *traj) {
+    if (!traj) return RD_E_INVALID;
+    Traj *t = (Traj *)traj;
+    Ctx *c = t->ctx;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    if (t->ws) {
+        c->resident -= std::min(c->resident, t->ws->bytes);
+        free_workspace(t->ws.get());
+        t->ws.reset();
+    }
+    for (size_t i = 0; i < c->admit_queue.size(); ++i)
+        if (c->admit_queue[i] == t) {
+            c->admit_queue.erase(c->admit_queue.begin() + i);
+            break;
+        }
+    for (size_t i = 0; i < c->trajs.size(); ++i)
+        if (c->trajs[i] == t) {
+            c->trajs.erase(c->trajs.begin() + i);
+            break;
+        }
+    if (t->u) (void)hipFree(t->u);
+    delete t;
+    return RD_OK;
+}
+
+}  // extern "C"

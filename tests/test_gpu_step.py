@@ -1,0 +1,172 @@
+"""GPU parity of rd_step (Algorithm 1 on the device) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import equations as oeq, pdhg as opdhg
+from paper_2305_03945_amd import workloads as wl
+from tests.rd_cases import max_abs, oracle_opts, oracle_problem, small_cfg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_03945_amd import rd as rdmod
+    return rdmod
+
+
+@pytest.fixture(scope="module")
+def ctx(rd):
+    c = rd.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def gpu_opts(rd, cfg, precision="fp64", tol=None, max_iter=10000, init="prev", inner_rtol=1e-3):
+    return rd.make_opts(tol=cfg["tol"] if tol is None else tol, max_iter=max_iter, tau_u=cfg["tau"],
+                        tau_p=cfg["tau"], omega=cfg["omega"], precision=precision, init=init,
+                        inner_rtol=inner_rtol)
+
+
+def compare_fp64(ctx, rd, cfg, U0, steps, tol=None, init="prev"):
+    """Run `steps` steps on both sides; iteration counts must match and the states agree to 1e-10."""
+    op = oracle_problem(cfg)
+    oo = oracle_opts(cfg, tol=tol, init=init)
+    p = rd.problem_from_config(cfg)
+    o = gpu_opts(rd, cfg, tol=tol, init=init)
+    Ug = dev(U0)
+    U = np.array(U0)
+    for k in range(steps):
+        r = opdhg.step(op, U, cfg["ht"], oo)
+        Ug, info = ctx.step(Ug, cfg["ht"], p, o)
+        assert info["status"] == "ok", (k, info)
+        assert info["iters"] == r.iters, (k, info, r.iters, r.residual)
+        assert info["residual"] == pytest.approx(r.residual, rel=1e-6, abs=1e-3 * (tol or cfg["tol"]))
+        err = max_abs(Ug.cpu().numpy(), r.U)
+        assert err <= 1e-10, (k, err)
+        U = r.U
+    return U
+
+
+def test_ac64_ten_steps_fp64(ctx, rd):
+    """The 64^2 periodic Allen-Cahn workload (eps = 0.05, h_t = 0.01, delta = 1e-10), all 10 steps."""
+    cfg = wl.CONFIGS["ac64"]
+    compare_fp64(ctx, rd, cfg, wl.initial_field(cfg), cfg["steps"])
+
+
+@pytest.mark.parametrize("kind", ["allen_cahn", "cahn_hilliard", "schnakenberg"])
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+@pytest.mark.parametrize("N", [16, 128])
+def test_step_fp64_matches_oracle(ctx, rd, kind, bc, N):
+    cfg = small_cfg(kind, N, bc)
+    tol = {"allen_cahn": 1e-8, "cahn_hilliard": 1e-5, "schnakenberg": 1e-7}[kind]
+    compare_fp64(ctx, rd, cfg, wl.initial_field(cfg, N=N, seed=7), 2, tol=tol)
+
+
+@pytest.mark.parametrize("kind", ["allen_cahn", "schnakenberg"])
+def test_step_fp64_prox_init_matches_oracle(ctx, rd, kind):
+    cfg = small_cfg(kind, 64, "periodic")
+    tol = 1e-8 if kind == "allen_cahn" else 1e-7
+    compare_fp64(ctx, rd, cfg, wl.initial_field(cfg, N=64, seed=8), 2, tol=tol, init="prox")
+
+
+@pytest.mark.parametrize("kind", ["allen_cahn", "cahn_hilliard", "schnakenberg"])
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+@pytest.mark.parametrize("N", [32, 256])
+def test_step_mixed_matches_oracle(ctx, rd, kind, bc, N):
+    cfg = small_cfg(kind, N, bc)
+    tol = {"allen_cahn": 1e-8, "cahn_hilliard": 1e-5, "schnakenberg": 1e-7}[kind]
+    op = oracle_problem(cfg)
+    U = wl.initial_field(cfg, N=N, seed=9)
+    p = rd.problem_from_config(cfg)
+    o = gpu_opts(rd, cfg, precision="mixed", tol=tol)
+    Ug = dev(U)
+    for k in range(2):
+        r = opdhg.step(op, U, cfg["ht"], oracle_opts(cfg, tol=tol))
+        Ug, info = ctx.step(Ug, cfg["ht"], p, o)
+        assert info["status"] == "ok", info
+        assert info["residual"] <= tol
+        assert info["outer"] >= 1
+        err = max_abs(Ug.cpu().numpy(), r.U)
+        assert err <= 1e-5, (k, err)
+        # The mixed result is a root of the same equation to the same tolerance.
+        W = oeq.F(op, Ug.cpu().numpy(), U, cfg["ht"])
+        assert oeq.residual_norm(op, W, cfg["ht"]) <= tol * (1 + 1e-6)
+        U = r.U
+        Ug = dev(U)
+
+
+def test_heat_step_exact_in_two_iterations(ctx, rd):
+    """f = 0, tau = omega = 1: the root after exactly two iterations (derived from the G-prox
+    dynamic; pins the transform scaling and symbol against the stencil)."""
+    N = 64
+    cfg = dict(kind="heat", N=N, L=1.0, bc="neumann", diff=(0.02,), ht=0.5, tol=0.0, tau=1.0, omega=1.0)
+    op = oracle_problem(cfg)
+    U = wl.uniform_field(N, -1, 1, 3)
+    p = rd.problem_from_config(cfg)
+    o = gpu_opts(rd, cfg, tol=0.0, max_iter=2)
+    Ug, info = ctx.step(dev(U), 0.5, p, o)
+    assert info["iters"] == 2
+    ref = opdhg.step(op, U, 0.5, opdhg.Options(tol=1e-13, tau_u=1.0, tau_p=1.0)).U
+    assert max_abs(Ug.cpu().numpy(), ref) <= 1e-12
+
+
+def test_bitwise_determinism_and_odd_symmetry(ctx, rd):
+    cfg = small_cfg("allen_cahn", 256, "periodic")
+    U = wl.initial_field(cfg, N=256, seed=11)
+    p = rd.problem_from_config(cfg)
+    o = gpu_opts(rd, cfg, tol=1e-8)
+    a, ia = ctx.step(dev(U), cfg["ht"], p, o)
+    b, ib = ctx.step(dev(U), cfg["ht"], p, o)
+    c, ic = ctx.step(dev(-U), cfg["ht"], p, o)
+    assert ia["iters"] == ib["iters"] == ic["iters"]
+    a, b, c = a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()
+    assert np.array_equal(a, b)
+    assert np.array_equal(c, -a)
+
+
+def test_cahn_hilliard_mass_drift_reported(ctx, rd):
+    cfg = small_cfg("cahn_hilliard", 128, "neumann")
+    U = wl.initial_field(cfg, N=128, seed=12)
+    p = rd.problem_from_config(cfg)
+    o = gpu_opts(rd, cfg, tol=1e-4)
+    Ug, info = ctx.step(dev(U), cfg["ht"], p, o)
+    drift = float(np.sum(Ug.cpu().numpy()) - np.sum(U))
+    assert abs(info["mass_drift"] - drift) <= 1e-9
+    assert abs(drift) <= 128 * cfg["ht"] * info["residual"] + 1e-12
+
+
+def test_noconv_and_nonfinite_and_invalid(ctx, rd):
+    cfg = small_cfg("allen_cahn", 64, "periodic")
+    U = wl.initial_field(cfg, N=64, seed=13)
+    p = rd.problem_from_config(cfg)
+    _, info = ctx.step(dev(U), cfg["ht"], p, gpu_opts(rd, cfg, tol=1e-12, max_iter=1))
+    assert info["status"] == "noconv" and info["iters"] == 1
+    Ubad = U.copy()
+    Ubad[3, 5] = np.nan
+    _, info = ctx.step(dev(Ubad), cfg["ht"], p, gpu_opts(rd, cfg))
+    assert info["status"] == "nonfinite"
+    _, info = ctx.step(dev(Ubad), cfg["ht"], p, gpu_opts(rd, cfg, precision="mixed"))
+    assert info["status"] == "nonfinite"
+    bad = rd.make_problem("allen_cahn", 48)
+    with pytest.raises(rd.RDError):
+        ctx.step(dev(np.zeros((48, 48))), 1e-3, bad, gpu_opts(rd, cfg))
+    with pytest.raises(rd.RDError):
+        ctx.step(dev(U), -1.0, p, gpu_opts(rd, cfg))
+
+
+def test_zero_iterations_when_start_is_converged(ctx, rd):
+    cfg = small_cfg("schnakenberg", 64, "periodic")
+    a, b = cfg["a"], cfg["sb"]
+    U = np.stack([np.full((64, 64), a + b), np.full((64, 64), b / (a + b) ** 2)])
+    Ug, info = ctx.step(dev(U), cfg["ht"], rd.problem_from_config(cfg), gpu_opts(rd, cfg, tol=1e-9))
+    assert info["iters"] == 0 and info["status"] == "ok"
+    assert np.array_equal(Ug.cpu().numpy(), U)

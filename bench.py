@@ -1,0 +1,181 @@
+#!/usr/bin/env python
+"""Benchmark of the implicit reaction-diffusion step on one MI355X.
+
+Workload: 2-D Allen-Cahn u_t = eps^2 Lap u + u - u^3 on the periodic unit
+square, 2048 x 2048 grid, eps = 0.01, backward Euler h_t = 1e-3, 200 steps,
+u0 ~ Uniform[-0.1, 0.1] (seed 1), stop at ||F/h_t||_2 <= 1e-6.  The same
+trajectory is run in plain FP64 and in the FP32-mixed precision (FP32 inner
+PDHG, FP64 residual / update passes).  A step is one rd_step call: the whole
+PDHG solve of one implicit time step, inputs already resident in HBM.
+
+Prints ONE JSON line: throughput in grid-point-iterations/s (grid points x PDHG
+iterations per second; mixed: FP32 inner iterations), p50/p99 step latency for
+both precisions, the dominant kernel against the HBM roofline (HIP-event launch
+durations on the launch stream) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PDHG grid-point-iters/s + p50/p99 step latency, FP32-mixed vs FP64 at 1e-5"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per grid point and launch of each kernel (one component):
+# every field the kernel must read or write once, nothing for tables or halos.
+#   cols   : read + write the spectrum (N^2 reals)
+#   rowinv : read spectrum, read P, write P, write P~
+#   upd    : read P~, read U_n (mixed: e_n and the FP32 copy of U), write U_{n+1}
+#   rowfwd : read U_{n+1} and U^k (mixed: e, U_b, r), write the spectrum
+BYTES_PER_POINT = {
+    "fp64": {"cols": 16, "rowinv": 32, "upd": 24, "rowfwd": 24},
+    "mixed": {"cols": 8, "rowinv": 16, "upd": 16, "rowfwd": 16},
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    s = sorted(xs)
+    if not s:
+        return None
+    k = (len(s) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(s) - 1)
+    return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+def run_precision(ctx, rd, torch, cfg, u0, prec, steps, warmup):
+    p = rd.problem_from_config(cfg)
+    o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], omega=cfg["omega"], precision=prec)
+    ht = cfg["ht"]
+    a = u0.clone()
+    b = torch.empty_like(a)
+    for _ in range(warmup):
+        ctx.step(a, ht, p, o, out=b)
+        a, b = b, a
+    a.copy_(u0)
+    torch.cuda.synchronize()
+    lat, iters, outer, first = [], 0, 0, None
+    statuses = {}
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ts = time.perf_counter()
+        _, info = ctx.step(a, ht, p, o, out=b)
+        lat.append(time.perf_counter() - ts)
+        iters += info["iters"]
+        outer += info["outer"]
+        statuses[info["status"]] = statuses.get(info["status"], 0) + 1
+        if k == 0:
+            first = b.clone()
+        a, b = b, a
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    N = cfg["N"]
+    return dict(
+        pt_iters_per_s=N * N * iters / wall, wall_s=wall, ms_per_step=1e3 * wall / steps,
+        p50_ms=1e3 * percentile(lat, 50), p99_ms=1e3 * percentile(lat, 99),
+        iters_total=iters, iters_per_step=iters / steps, outer_total=outer, status=statuses,
+    ), first, a
+
+
+def cpu_oracle_sample(cfg, u0_np):
+    """The FP64 oracle (Algorithm 1, numpy) on the first step of the workload."""
+    from oracle import pdhg as opdhg
+    from tests.rd_cases import oracle_opts, oracle_problem
+    t0, c0 = time.perf_counter(), os.times()
+    r = opdhg.step(oracle_problem(cfg), u0_np, cfg["ht"], oracle_opts(cfg))
+    wall = time.perf_counter() - t0
+    c1 = os.times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    N = cfg["N"]
+    return r, dict(value=N * N * r.iters / wall, unit="grid-point-iters/s", cores=max(1, round(cpu / wall)),
+                   kind="oracle", wall_s=round(wall, 3),
+                   sample="first implicit step of the %dx%d Allen-Cahn workload, %d PDHG iterations to the "
+                          "workload tolerance" % (N, N, r.iters))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ac2048")
+    ap.add_argument("--reps", type=int, default=20, help="launches per kernel for the HIP-event timing")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2305_03945_amd import rd, workloads as wl
+
+    cfg = dict(wl.CONFIGS[args.workload])
+    N = cfg["N"]
+    u0_np = wl.initial_field(cfg)
+    u0 = torch.tensor(u0_np, dtype=torch.float64, device="cuda")
+    ctx = rd.Context(0)
+    results, firsts, finals = {}, {}, {}
+    for prec in ("fp64", "mixed"):
+        log("timing %s: %d warmup + %d steps on %dx%d" % (prec, args.warmup, args.steps, N, N))
+        results[prec], firsts[prec], finals[prec] = run_precision(ctx, rd, torch, cfg, u0, prec, args.steps,
+                                                                  args.warmup)
+        log("  %s" % json.dumps(results[prec]))
+
+    # Per-kernel launch durations (HIP events on the launch stream).
+    kernels = {}
+    p = rd.problem_from_config(cfg)
+    for prec in ("fp64", "mixed"):
+        o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], precision=prec)
+        ms = ctx.profile_iteration(u0, cfg["ht"], p, o, reps=args.reps)
+        kernels[prec] = {}
+        for k, t in ms.items():
+            nbytes = BYTES_PER_POINT[prec][k] * N * N
+            kernels[prec][k] = dict(ms=t, bytes=nbytes, gbs=nbytes / (t * 1e-3) / 1e9)
+        log("  kernels %s: %s" % (prec, json.dumps(kernels[prec])))
+    head = "mixed"
+    dom = max(kernels[head], key=lambda k: kernels[head][k]["ms"])
+    dk = kernels[head][dom]
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(dk["gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                    bytes_per_launch=dk["bytes"], ms_per_launch=dk["ms"])
+
+    accuracy = {}
+    cpu = None
+    if not args.no_cpu:
+        log("cpu oracle: first step at %dx%d" % (N, N))
+        ref, cpu = cpu_oracle_sample(cfg, u0_np)
+        for prec in ("fp64", "mixed"):
+            accuracy["%s_step1_maxabs_vs_oracle" % prec] = float(np.max(np.abs(firsts[prec].cpu().numpy() - ref.U)))
+        accuracy["oracle_step1_iters"] = ref.iters
+    accuracy["mixed_vs_fp64_final_maxabs"] = float((finals["mixed"] - finals["fp64"]).abs().max().item())
+
+    mx, f64 = results["mixed"], results["fp64"]
+    line = {
+        "metric": METRIC, "value": mx["pt_iters_per_s"], "unit": "grid-point-iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": mx["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64 (mixed)", "data": "synthetic",
+        "config": {"workload": "allen_cahn_%d_periodic" % N, "N": N, "eps": float(cfg["diff"][0]) ** 0.5,
+                   "ht": cfg["ht"], "steps": cfg["steps"], "tol_l2": cfg["tol"], "tau": cfg["tau"],
+                   "u0": "uniform[-0.1,0.1] seed %d" % cfg["seed"]},
+        "p50_ms": mx["p50_ms"], "p99_ms": mx["p99_ms"],
+        "mixed": mx, "fp64": f64,
+        "speedup_mixed_vs_fp64": f64["wall_s"] / mx["wall_s"],
+        "accuracy": accuracy, "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

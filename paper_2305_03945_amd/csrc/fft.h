@@ -14,13 +14,17 @@
 //    The inverse rebuilds V_k = conj(w_k) (X_k - i X_{N-k}) (X_N = 0) and applies
 //    an inverse FFT.  Two real sequences are again packed into one complex FFT.
 //
-// FFTs are Stockham autosort passes (radix 8, then one radix-4 or radix-2 pass),
+// The complex FFTs themselves are in fft16.h (radix-16 Stockham passes in LDS);
 // forward sign -1, both directions unnormalised; the 1/N^2 of the 2-D inverse is
-// folded into the symbol multiplier.
+// folded into the symbol multiplier.  This file holds the small DFT kernels and
+// the pair / cosine pre- and post-processing over padded LDS regions.
 #pragma once
 #include "rd_dev.h"
 
 namespace rdk {
+
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+template <int LOGN> __host__ __device__ constexpr int lds_region() { return (1 << LOGN) + (1 << LOGN) / 16; }
 
 template <typename T, int DIR> __device__ __forceinline__ cplx<T> rot90(cplx<T> a) {
     // multiply by exp(DIR i pi / 2): -i for the forward transform, +i for the inverse
@@ -69,104 +73,37 @@ template <typename T, int R, int DIR> __device__ __forceinline__ void dft(cplx<T
     else dft2<T, DIR>(v);
 }
 
-// One Stockham pass of radix R over a length-N region (NS = product of the
-// radices of the passes already done).  Butterfly j reads x[j + r N/R], twiddles
-// input r by W_{NS R}^{r k} (k = j mod NS), applies DFT_R and writes output q to
-// ((j - k) R + k) + q NS.  Reads complete (barrier) before any write.
-template <typename T, int LOGN, int R, int NS, int DIR>
-__device__ __forceinline__ void stockham_pass(cplx<T> *x, int lane, bool active,
-                                              const cplx<T> *__restrict__ tw) {
-    constexpr int N = 1 << LOGN;
-    constexpr int TEAM = fft_team<LOGN>();
-    constexpr int NB = N / R;
-    constexpr int BPT = NB / TEAM;
-    constexpr int TWSTEP = N / (NS * R);
-    static_assert(BPT >= 1, "team larger than butterfly count");
-    cplx<T> v[BPT][R];
-    if (active) {
-#pragma unroll
-        for (int b = 0; b < BPT; ++b) {
-            const int j = lane + b * TEAM;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = x[j + r * NB];
-            if constexpr (NS > 1) {
-                const int k = j & (NS - 1);
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    cplx<T> w = tw[r * k * TWSTEP];
-                    if constexpr (DIR > 0) w.im = -w.im;
-                    v[b][r] = cmul(v[b][r], w);
-                }
-            }
-            dft<T, R, DIR>(v[b]);
-        }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int b = 0; b < BPT; ++b) {
-            const int j = lane + b * TEAM;
-            const int k = j & (NS - 1);
-            const int base = (j - k) * R + k;
-#pragma unroll
-            for (int q = 0; q < R; ++q) x[base + q * NS] = v[b][q];
-        }
-    }
-    __syncthreads();
-}
+// LDS regions hold N complex values with one padding slot per 16 (fft16.h):
+// complex element i of region r lives at r * lds_region<LOGN>() + lds_pad(i).
+template <int LOGN> __device__ __forceinline__ int rix(int reg, int i) { return reg * lds_region<LOGN>() + lds_pad(i); }
 
-template <typename T, int LOGN, int DIR, int DONE>
-__device__ __forceinline__ void stockham_all(cplx<T> *x, int lane, bool active, const cplx<T> *tw) {
-    if constexpr (DONE < LOGN) {
-        constexpr int REM = LOGN - DONE;
-        constexpr int R = REM >= 3 ? 8 : (REM == 2 ? 4 : 2);
-        constexpr int LOGR = R == 8 ? 3 : (R == 4 ? 2 : 1);
-        stockham_pass<T, LOGN, R, (1 << DONE), DIR>(x, lane, active, tw);
-        stockham_all<T, LOGN, DIR, DONE + LOGR>(x, lane, active, tw);
-    }
-}
-
-// In-place length-N FFTs of NREG regions (region i at buf + i * N) by the whole
-// workgroup; teams of fft_team<LOGN>() threads take regions round-robin.
-// Ends with a barrier.  DIR = -1 forward, +1 inverse (unnormalised).
-template <typename T, int LOGN, int DIR, int NREG>
-__device__ __forceinline__ void wg_fft(cplx<T> *buf, const cplx<T> *__restrict__ tw) {
-    constexpr int N = 1 << LOGN;
-    constexpr int TEAM = fft_team<LOGN>();
-    constexpr int NTEAMS = NT / TEAM;
-    const int team = threadIdx.x / TEAM;
-    const int lane = threadIdx.x % TEAM;
-#pragma unroll 1
-    for (int g = 0; g < NREG; g += NTEAMS) {
-        const int reg = g + team;
-        const bool active = reg < NREG;
-        stockham_all<T, LOGN, DIR, 0>(buf + (active ? reg : 0) * N, lane, active, tw);
-    }
+// Real element m (< 2N) of a region viewed as 2N reals (re, im interleaved).
+template <typename T, int LOGN> __device__ __forceinline__ T &rreal(cplx<T> *buf, int reg, int m) {
+    return reinterpret_cast<T *>(&buf[rix<LOGN>(reg, m >> 1)])[m & 1];
 }
 
 // Work items for the pair steps: item (region, l), l < N/2, owns bins l and N-l
 // (item 0 owns bins 0 and N/2).
-template <int LOGN, int NREG> constexpr int pair_items_per_thread() {
+template <int LOGN, int NREG, int NTH> constexpr int pair_items_per_thread() {
     constexpr int total = NREG * ((1 << LOGN) / 2);
-    return (total + NT - 1) / NT;
+    return (total + NTH - 1) / NTH;
 }
 
 // ---- row pass, forward: packed pair spectrum Z -> two rows of slots (in place).
 // Periodic: slots of row a hold (A_0, A_{N/2}) then A_1..A_{N/2-1}; row b likewise.
 // Neumann: the region, viewed as 2N reals, holds X_a[0..N) then X_b[0..N).
-template <typename T, int LOGN, int BC, int NREG>
+template <typename T, int LOGN, int BC, int NREG, int NTH>
 __device__ __forceinline__ void rows_post_forward(cplx<T> *buf, const cplx<T> *__restrict__ twd) {
     constexpr int N = 1 << LOGN, H = N / 2;
-    constexpr int IPT = pair_items_per_thread<LOGN, NREG>();
+    constexpr int IPT = pair_items_per_thread<LOGN, NREG, NTH>();
     cplx<T> oa[IPT], ob[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int it = threadIdx.x + i * NT;
+        const int it = threadIdx.x + i * NTH;
         if (it >= NREG * H) break;
         const int reg = it / H, l = it % H;
-        const cplx<T> *z = buf + reg * N;
         if (l == 0) {
-            const cplx<T> z0 = z[0], zh = z[H];
+            const cplx<T> z0 = buf[rix<LOGN>(reg, 0)], zh = buf[rix<LOGN>(reg, H)];
             if constexpr (BC == BC_P) {
                 oa[i] = {z0.re, zh.re};
                 ob[i] = {z0.im, zh.im};
@@ -176,7 +113,7 @@ __device__ __forceinline__ void rows_post_forward(cplx<T> *buf, const cplx<T> *_
                 ob[i] = {z0.im, s * zh.im};
             }
         } else {
-            const cplx<T> zl = z[l], zn = z[N - l];
+            const cplx<T> zl = buf[rix<LOGN>(reg, l)], zn = buf[rix<LOGN>(reg, N - l)];
             const cplx<T> A = {(zl.re + zn.re) * (T)0.5, (zl.im - zn.im) * (T)0.5};
             const cplx<T> B = {(zl.im + zn.im) * (T)0.5, (zn.re - zl.re) * (T)0.5};
             if constexpr (BC == BC_P) {
@@ -193,22 +130,23 @@ __device__ __forceinline__ void rows_post_forward(cplx<T> *buf, const cplx<T> *_
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int it = threadIdx.x + i * NT;
+        const int it = threadIdx.x + i * NTH;
         if (it >= NREG * H) break;
         const int reg = it / H, l = it % H;
-        cplx<T> *z = buf + reg * N;
         if constexpr (BC == BC_P) {
-            z[l] = oa[i];
-            z[H + l] = ob[i];
+            buf[rix<LOGN>(reg, l)] = oa[i];
+            buf[rix<LOGN>(reg, H + l)] = ob[i];
         } else {
-            T *xa = reinterpret_cast<T *>(z);
-            T *xb = xa + N;
             if (l == 0) {
-                xa[0] = oa[i].re; xa[H] = oa[i].im;
-                xb[0] = ob[i].re; xb[H] = ob[i].im;
+                rreal<T, LOGN>(buf, reg, 0) = oa[i].re;
+                rreal<T, LOGN>(buf, reg, H) = oa[i].im;
+                rreal<T, LOGN>(buf, reg, N) = ob[i].re;
+                rreal<T, LOGN>(buf, reg, N + H) = ob[i].im;
             } else {
-                xa[l] = oa[i].re; xa[N - l] = oa[i].im;
-                xb[l] = ob[i].re; xb[N - l] = ob[i].im;
+                rreal<T, LOGN>(buf, reg, l) = oa[i].re;
+                rreal<T, LOGN>(buf, reg, N - l) = oa[i].im;
+                rreal<T, LOGN>(buf, reg, N + l) = ob[i].re;
+                rreal<T, LOGN>(buf, reg, 2 * N - l) = ob[i].im;
             }
         }
     }
@@ -216,19 +154,18 @@ __device__ __forceinline__ void rows_post_forward(cplx<T> *buf, const cplx<T> *_
 }
 
 // ---- row pass, inverse: two rows of slots -> packed pair spectrum Z (in place).
-template <typename T, int LOGN, int BC, int NREG>
+template <typename T, int LOGN, int BC, int NREG, int NTH>
 __device__ __forceinline__ void rows_pre_inverse(cplx<T> *buf, const cplx<T> *__restrict__ twd) {
     constexpr int N = 1 << LOGN, H = N / 2;
-    constexpr int IPT = pair_items_per_thread<LOGN, NREG>();
+    constexpr int IPT = pair_items_per_thread<LOGN, NREG, NTH>();
     cplx<T> zl_out[IPT], zn_out[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int it = threadIdx.x + i * NT;
+        const int it = threadIdx.x + i * NTH;
         if (it >= NREG * H) break;
         const int reg = it / H, l = it % H;
-        const cplx<T> *z = buf + reg * N;
         if constexpr (BC == BC_P) {
-            const cplx<T> a = z[l], b = z[H + l];
+            const cplx<T> a = buf[rix<LOGN>(reg, l)], b = buf[rix<LOGN>(reg, H + l)];
             if (l == 0) {
                 zl_out[i] = {a.re, b.re};   // Z_0 = A_0 + i B_0
                 zn_out[i] = {a.im, b.im};   // Z_{N/2}
@@ -237,16 +174,15 @@ __device__ __forceinline__ void rows_pre_inverse(cplx<T> *buf, const cplx<T> *__
                 zn_out[i] = {a.re + b.im, b.re - a.im};
             }
         } else {
-            const T *xa = reinterpret_cast<const T *>(z);
-            const T *xb = xa + N;
             if (l == 0) {
                 const T r2 = (T)1.41421356237309504880168872420969808;
-                zl_out[i] = {xa[0], xb[0]};
-                zn_out[i] = {r2 * xa[H], r2 * xb[H]};
+                zl_out[i] = {rreal<T, LOGN>(buf, reg, 0), rreal<T, LOGN>(buf, reg, N)};
+                zn_out[i] = {r2 * rreal<T, LOGN>(buf, reg, H), r2 * rreal<T, LOGN>(buf, reg, N + H)};
             } else {
                 const cplx<T> wc = cconj(twd[l]);
-                const cplx<T> va = cmul(wc, cplx<T>{xa[l], -xa[N - l]});
-                const cplx<T> vb = cmul(wc, cplx<T>{xb[l], -xb[N - l]});
+                const cplx<T> va = cmul(wc, cplx<T>{rreal<T, LOGN>(buf, reg, l), -rreal<T, LOGN>(buf, reg, N - l)});
+                const cplx<T> vb =
+                    cmul(wc, cplx<T>{rreal<T, LOGN>(buf, reg, N + l), -rreal<T, LOGN>(buf, reg, 2 * N - l)});
                 zl_out[i] = {va.re - vb.im, va.im + vb.re};
                 zn_out[i] = {va.re + vb.im, vb.re - va.im};
             }
@@ -255,12 +191,11 @@ __device__ __forceinline__ void rows_pre_inverse(cplx<T> *buf, const cplx<T> *__
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int it = threadIdx.x + i * NT;
+        const int it = threadIdx.x + i * NTH;
         if (it >= NREG * H) break;
         const int reg = it / H, l = it % H;
-        cplx<T> *z = buf + reg * N;
-        z[l] = zl_out[i];
-        z[l == 0 ? H : N - l] = zn_out[i];
+        buf[rix<LOGN>(reg, l)] = zl_out[i];
+        buf[rix<LOGN>(reg, l == 0 ? H : N - l)] = zn_out[i];
     }
     __syncthreads();
 }
@@ -280,36 +215,37 @@ __device__ __forceinline__ double symbol_mult(const double *__restrict__ eig, in
 // column j packs kx = 2j (real) and kx = 2j + 1 (imaginary), both cosine
 // coefficients.  Each item rewrites its own two bins, so no barrier is needed
 // between reading and writing.
-template <typename T, int LOGN, int BC, int NREG>
-__device__ __forceinline__ void cols_apply_symbol(cplx<T> *buf, int job0, int njobs, const Slot &s,
+template <typename T, int LOGN, int BC, int NREG, int NTH>
+__device__ __forceinline__ void cols_apply_symbol(cplx<T> *buf, int job0, int njobs, SlotRef s,
                                                   const cplx<T> *__restrict__ twd) {
     constexpr int N = 1 << LOGN, H = N / 2;
-    constexpr int IPT = pair_items_per_thread<LOGN, NREG>();
+    constexpr int IPT = pair_items_per_thread<LOGN, NREG, NTH>();
     const double invN2 = 1.0 / ((double)N * (double)N);
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-        const int it = threadIdx.x + i * NT;
+        const int it = threadIdx.x + i * NTH;
         if (it >= NREG * H) break;
         const int reg = it / H, l = it % H;
         if (reg >= njobs) continue;
         const int job = job0 + reg;
         const int c = job / H, j = job % H;
         const double al = s.alpha[c], be = s.beta[c];
-        cplx<T> *z = buf + reg * N;
         const int nl = (l == 0) ? H : N - l;
-        const cplx<T> zl = z[l], zn = z[nl];
+        cplx<T> &zlr = buf[rix<LOGN>(reg, l)];
+        cplx<T> &znr = buf[rix<LOGN>(reg, nl)];
+        const cplx<T> zl = zlr, zn = znr;
         if constexpr (BC == BC_P) {
             if (j > 0) {
                 const T m1 = (T)symbol_mult(s.eig, j, l, al, be, invN2);
                 const T m2 = (T)symbol_mult(s.eig, j, nl, al, be, invN2);
-                z[l] = {zl.re * m1, zl.im * m1};
-                z[nl] = {zn.re * m2, zn.im * m2};
+                zlr = {zl.re * m1, zl.im * m1};
+                znr = {zn.re * m2, zn.im * m2};
             } else if (l == 0) {
                 // bins 0 and N/2 of the packed (kx = 0, kx = N/2) column: real pairs
-                z[0] = {zl.re * (T)symbol_mult(s.eig, 0, 0, al, be, invN2),
-                        zl.im * (T)symbol_mult(s.eig, H, 0, al, be, invN2)};
-                z[H] = {zn.re * (T)symbol_mult(s.eig, 0, H, al, be, invN2),
-                        zn.im * (T)symbol_mult(s.eig, H, H, al, be, invN2)};
+                zlr = {zl.re * (T)symbol_mult(s.eig, 0, 0, al, be, invN2),
+                       zl.im * (T)symbol_mult(s.eig, H, 0, al, be, invN2)};
+                znr = {zn.re * (T)symbol_mult(s.eig, 0, H, al, be, invN2),
+                       zn.im * (T)symbol_mult(s.eig, H, H, al, be, invN2)};
             } else {
                 const T ma = (T)symbol_mult(s.eig, 0, l, al, be, invN2);
                 const T mb = (T)symbol_mult(s.eig, H, l, al, be, invN2);
@@ -317,16 +253,16 @@ __device__ __forceinline__ void cols_apply_symbol(cplx<T> *buf, int job0, int nj
                 cplx<T> B = {(zl.im + zn.im) * (T)0.5, (zn.re - zl.re) * (T)0.5};
                 A = {A.re * ma, A.im * ma};
                 B = {B.re * mb, B.im * mb};
-                z[l] = {A.re - B.im, A.im + B.re};
-                z[nl] = {A.re + B.im, B.re - A.im};
+                zlr = {A.re - B.im, A.im + B.re};
+                znr = {A.re + B.im, B.re - A.im};
             }
         } else {
             const int ka = 2 * j, kb = 2 * j + 1;
             if (l == 0) {
-                z[0] = {zl.re * (T)symbol_mult(s.eig, ka, 0, al, be, invN2),
-                        zl.im * (T)symbol_mult(s.eig, kb, 0, al, be, invN2)};
-                z[H] = {zn.re * (T)symbol_mult(s.eig, ka, H, al, be, invN2),
-                        zn.im * (T)symbol_mult(s.eig, kb, H, al, be, invN2)};
+                zlr = {zl.re * (T)symbol_mult(s.eig, ka, 0, al, be, invN2),
+                       zl.im * (T)symbol_mult(s.eig, kb, 0, al, be, invN2)};
+                znr = {zn.re * (T)symbol_mult(s.eig, ka, H, al, be, invN2),
+                       zn.im * (T)symbol_mult(s.eig, kb, H, al, be, invN2)};
             } else {
                 const cplx<T> w = twd[l];
                 const cplx<T> A = {(zl.re + zn.re) * (T)0.5, (zl.im - zn.im) * (T)0.5};
@@ -340,8 +276,8 @@ __device__ __forceinline__ void cols_apply_symbol(cplx<T> *buf, int job0, int nj
                 const cplx<T> wc = cconj(w);
                 const cplx<T> va = cmul(wc, cplx<T>{xal, -xan});
                 const cplx<T> vb = cmul(wc, cplx<T>{xbl, -xbn});
-                z[l] = {va.re - vb.im, va.im + vb.re};
-                z[nl] = {va.re + vb.im, vb.re - va.im};
+                zlr = {va.re - vb.im, va.im + vb.re};
+                znr = {va.re + vb.im, vb.re - va.im};
             }
         }
     }

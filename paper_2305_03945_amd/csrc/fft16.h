@@ -1,0 +1,147 @@
+// Workgroup FFT with radix-16 passes, 16 values per thread.
+//
+// A length-N transform (N = 2^LOGN, 16 <= N <= 4096) is done by N/16 threads
+// (one wave or less for N <= 1024, several waves above), in an LDS region of
+// N complex values laid out with one padding slot per 16 (index i at
+// i + i/16), which keeps the stride-R writes of a Stockham pass off a single
+// bank group.  Passes are Stockham autosort passes of radix 16, then one pass
+// of radix 8, 4 or 2 for the remaining bits; each thread runs 16/R butterflies
+// of a radix-R pass.  The twiddles W^{r k}, r = 1..R-1, of a butterfly are
+// products of the gathered powers W^{k}, W^{2k}, W^{4k}, W^{8k}, so a
+// butterfly gathers at most 4 table entries and each twiddle carries at most
+// 3 roundings.
+#pragma once
+#include "fft.h"
+
+namespace rdk {
+
+template <typename T, int DIR> __device__ __forceinline__ void dft16(cplx<T> *v) {
+    // radix-4 x radix-4: columns of 4 (stride 4), twiddle W16^{n1 k2}, rows of 4
+    cplx<T> a[4][4];
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) {
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) a[n1][n2] = v[n1 + 4 * n2];
+        dft4<T, DIR>(a[n1]);   // over n2 -> k2
+    }
+    const T c1 = (T)0.923879532511286756128183189396788934;   // cos(pi/8)
+    const T s1 = (T)0.382683432365089771728459984030398867;   // sin(pi/8)
+    const T r2 = (T)0.707106781186547524400844362104849039;
+    const T d = (T)DIR;
+    // W16^{m} = cos(2 pi m/16) + DIR i sin(2 pi m/16), for m = n1 * k2
+    auto tw16 = [&](int m) -> cplx<T> {
+        switch (m) {
+        case 1: return {c1, d * s1};
+        case 2: return {r2, d * r2};
+        case 3: return {s1, d * c1};
+        case 4: return {(T)0, d};
+        case 6: return {-r2, d * r2};
+        case 9: return {-c1, -d * s1};
+        default: return {(T)1, (T)0};
+        }
+    };
+#pragma unroll
+    for (int n1 = 1; n1 < 4; ++n1)
+#pragma unroll
+        for (int k2 = 1; k2 < 4; ++k2) a[n1][k2] = cmul(a[n1][k2], tw16(n1 * k2));
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+        cplx<T> b[4] = {a[0][k2], a[1][k2], a[2][k2], a[3][k2]};
+        dft4<T, DIR>(b);   // over n1 -> k1
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) v[k2 + 4 * k1] = b[k1];
+    }
+}
+
+template <typename T, int R, int DIR> __device__ __forceinline__ void dftR(cplx<T> *v) {
+    if constexpr (R == 16) dft16<T, DIR>(v);
+    else if constexpr (R == 8) dft8<T, DIR>(v);
+    else if constexpr (R == 4) dft4<T, DIR>(v);
+    else dft2<T, DIR>(v);
+}
+
+// One Stockham pass of radix R (NS = product of earlier radices).  Butterfly j
+// reads x[j + r N/R], twiddles input r by W_{NS R}^{r k} (k = j mod NS), applies
+// DFT_R, and writes output q to ((j - k) R + k) + q NS.
+template <typename T, int LOGN, int R, int NS, int DIR>
+__device__ __forceinline__ void pass16(cplx<T> *x, int t, bool active, const cplx<T> *__restrict__ tw) {
+    constexpr int N = 1 << LOGN;
+    constexpr int TPF = N / 16;      // threads per transform
+    constexpr int NB = N / R;        // butterflies
+    constexpr int BPT = 16 / R;      // butterflies per thread
+    constexpr int TWSTEP = N / (NS * R);
+    cplx<T> v[BPT][R];
+    if (active) {
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) {
+            const int j = t + b * TPF;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = x[lds_pad(j + r * NB)];
+            if constexpr (NS > 1) {
+                const int k = j & (NS - 1);
+                cplx<T> p[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if ((1 << e) < R) {
+                        p[e] = tw[((k * TWSTEP) << e) & (N - 1)];
+                        if constexpr (DIR > 0) p[e].im = -p[e].im;
+                    }
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cplx<T> w = {(T)1, (T)0};
+                    bool first = true;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (r & (1 << e)) {
+                            w = first ? p[e] : cmul(w, p[e]);
+                            first = false;
+                        }
+                    v[b][r] = cmul(v[b][r], w);
+                }
+            }
+            dftR<T, R, DIR>(v[b]);
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) {
+            const int j = t + b * TPF;
+            const int k = j & (NS - 1);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) x[lds_pad(base + q * NS)] = v[b][q];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int LOGN, int DIR, int DONE>
+__device__ __forceinline__ void passes16(cplx<T> *x, int t, bool active, const cplx<T> *tw) {
+    if constexpr (DONE < LOGN) {
+        constexpr int REM = LOGN - DONE;
+        constexpr int R = REM >= 4 ? 16 : (1 << REM);
+        constexpr int LOGR = REM >= 4 ? 4 : REM;
+        pass16<T, LOGN, R, (1 << DONE), DIR>(x, t, active, tw);
+        passes16<T, LOGN, DIR, DONE + LOGR>(x, t, active, tw);
+    }
+}
+
+// In-place transforms of NREG regions (region i at buf + i * lds_region<LOGN>(),
+// padded indexing) by a workgroup of NTH threads; teams of N/16 threads take
+// regions round-robin.  Ends with a barrier.  DIR -1 forward, +1 inverse.
+template <typename T, int LOGN, int DIR, int NREG, int NTH>
+__device__ __forceinline__ void wg_fft16(cplx<T> *buf, const cplx<T> *__restrict__ tw) {
+    constexpr int TPF = (1 << LOGN) / 16;
+    static_assert(NTH % TPF == 0 || TPF > NTH, "team must divide the workgroup");
+    constexpr int NTEAMS = NTH / TPF;
+    const int team = threadIdx.x / TPF, t = threadIdx.x % TPF;
+#pragma unroll 1
+    for (int g = 0; g < NREG; g += NTEAMS) {
+        const int reg = g + team;
+        const bool active = reg < NREG;
+        passes16<T, LOGN, DIR, 0>(buf + (active ? reg : 0) * lds_region<LOGN>(), t, active, tw);
+    }
+}
+
+}  // namespace rdk

@@ -16,7 +16,7 @@
 // Every kernel first reads the slot's State and returns at once when the slot
 // is finished, so a host may enqueue more iterations than needed.
 #pragma once
-#include "fft.h"
+#include "fft16.h"
 
 namespace rdk {
 
@@ -64,7 +64,7 @@ __device__ __forceinline__ void prox_schnak(double cu, double cv, double ht, dou
 // F(U) in precision V (Sec. 2.1 eq. 12; Sec. 3.2 eq. 29 with the PDE's sign of the
 // biharmonic term; Sec. 3.4.1).  ukc: U^k at the point, per component.
 template <int EQ, typename V, class Acc>
-__device__ __forceinline__ void eval_F(const Slot &s, Acc u, const V *ukc, V *W, V *Uc) {
+__device__ __forceinline__ void eval_F(SlotRef s, Acc u, const V *ukc, V *W, V *Uc) {
     const V ht = (V)s.ht, ih2 = (V)s.inv_h2;
     if constexpr (EQ == EQ_LAP5) {
         const V u0 = u(0, 0, 0);
@@ -104,7 +104,7 @@ __device__ __forceinline__ void eval_F(const Slot &s, Acc u, const V *ukc, V *W,
 //   Schnakenberg: (U+e_u)^2 (V+e_v) - U^2 V = 2UV e_u + U^2 e_v + V e_u^2 + 2U e_u e_v + e_u^2 e_v
 // e: accessor of the correction, ub: accessor of the FP32 copy of U.
 template <int EQ, class AccE, class AccU>
-__device__ __forceinline__ void eval_Ftilde(const Slot &s, AccE e, AccU ub, const float *rc, float *W) {
+__device__ __forceinline__ void eval_Ftilde(SlotRef s, AccE e, AccU ub, const float *rc, float *W) {
     const float ht = (float)s.ht, ih2 = (float)s.inv_h2;
     if constexpr (EQ == EQ_LAP5) {
         const float e0 = e(0, 0, 0), U = ub(0, 0, 0);
@@ -138,7 +138,7 @@ __device__ __forceinline__ void eval_Ftilde(const Slot &s, AccE e, AccU ub, cons
 // grad F(U)^T P~ at one point (eq. 23; eq. 32 with the PDE's sign; Sec. 3.4.1).
 // p: accessor of P~; Uc: U at the point per component.
 template <int EQ, typename V, class Acc>
-__device__ __forceinline__ void eval_adjoint(const Slot &s, Acc p, const V *Uc, V *out) {
+__device__ __forceinline__ void eval_adjoint(SlotRef s, Acc p, const V *Uc, V *out) {
     const V ht = (V)s.ht, ih2 = (V)s.inv_h2;
     if constexpr (EQ == EQ_LAP5) {
         const V p0 = p(0, 0, 0);
@@ -193,7 +193,7 @@ __device__ __forceinline__ bool finite_(double x) { return x == x && x - x == 0.
 
 // Slot stop decision after a residual reduction (thread 0 of the last workgroup).
 template <int KIND, int C>
-__device__ __forceinline__ void finalize(const Slot &s, const double *sumsq, const double *mass) {
+__device__ __forceinline__ void finalize(SlotRef s, const double *sumsq, const double *mass) {
     State *st = s.st;
     double res = 0.0, m = 0.0;
 #pragma unroll
@@ -273,47 +273,176 @@ __device__ __forceinline__ void finalize(const Slot &s, const double *sumsq, con
     __threadfence();
 }
 
-// Write this workgroup's partial sums; the last workgroup of the slot to arrive
-// reduces all of them in block order and runs finalize<KIND>.
-template <int KIND, int C>
-__device__ __forceinline__ void reduce_and_finalize(const Slot &s, double *acc /* 2C */, double *scratch) {
-    __shared__ int am_last;
+// Write this workgroup's partial sums (squared residual norm and sum(U - U^k)
+// per component) to the slot's partials array.  The stop decision is taken by
+// k_finalize, launched right after, which reads them after the kernel boundary.
+template <int C>
+__device__ __forceinline__ void write_partials(SlotRef s, double *acc /* 2C */, double *scratch) {
     block_sum<2 * C>(acc, scratch);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < 2 * C; ++k) s.partials[blockIdx.x * (2 * C) + k] = acc[k];
-        __threadfence();
-        const unsigned prev = atomicAdd(&s.st->counter, 1u);
-        am_last = (prev == gridDim.x - 1) ? 1 : 0;
     }
-    __syncthreads();
-    if (!am_last) return;
-    __threadfence();
+}
+
+// Whether a launch of this kind has nothing to do for the slot (same answer in
+// every wave: the State does not change during the launch).
+template <int KIND> __device__ __forceinline__ bool skip_launch(StateRef sst) {
+    if constexpr (KIND == K_INIT64 || KIND == K_OUTER_INIT) return false;
+    else if constexpr (KIND == K_OUTER_UPD) return sst.outer_done || !sst.done;
+    else return sst.done != 0;
+}
+
+// ---------------------------------------------------------------- stop decision
+// One workgroup per slot: reduce the row pass's per-workgroup partial sums in
+// block order (deterministic), then take the decision of finalize<KIND>.  Skips
+// exactly when the row-pass launch of the same kind skipped.
+template <int KIND, int C>
+__global__ __launch_bounds__(NT) void k_finalize(Slot *const *slots) {
+    __shared__ double scratch[2 * C * (NT / 64)];
+    SlotRef s = slot_of(slots);
+    StateRef sst = state_of(s);
+    if (skip_launch<KIND>(sst)) return;
     double v[2 * C];
 #pragma unroll
     for (int k = 0; k < 2 * C; ++k) v[k] = 0.0;
-    for (int bl = threadIdx.x; bl < (int)gridDim.x; bl += NT) {
+    for (int bl = threadIdx.x; bl < s.nblk_rows; bl += NT) {
 #pragma unroll
-        for (int k = 0; k < 2 * C; ++k)
-            v[k] += __hip_atomic_load(&s.partials[bl * (2 * C) + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < 2 * C; ++k) v[k] += s.partials[bl * (2 * C) + k];
     }
     block_sum<2 * C>(v, scratch);
     if (threadIdx.x == 0) finalize<KIND, C>(s, v, v + C);
 }
 
-// Read the slot state into LDS and decide whether this launch has work.
-template <int KIND> __device__ __forceinline__ bool load_state(const Slot &s, State &sst) {
-    __shared__ int skip;
-    if (threadIdx.x == 0) {
-        sst = *s.st;
-        int sk;
-        if (KIND == K_INIT64 || KIND == K_OUTER_INIT) sk = 0;
-        else if (KIND == K_OUTER_UPD) sk = (sst.outer_done || !sst.done) ? 1 : 0;
-        else sk = sst.done;
-        skip = sk;
+
+// The residual-type quantity a row-forward pass transforms, at grid point
+// (y, x), for every component: W = F(U) (FP64 kinds) or the FP32 inner residual,
+// plus the side effects of the kind (initial copies, outer-pass state) and the
+// point's contributions to the squared norm (acc[c]) and to sum(U - U^k) (acc[C + c]).
+template <typename T, int LOGN, int BC, int EQ, int KIND>
+__device__ __forceinline__ void produce_W(SlotRef s, StateRef sst, int y, int x, T *wv, double *acc) {
+    constexpr int N = 1 << LOGN;
+    constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
+    constexpr size_t NN = (size_t)N * N;
+    const int it = sst.iters;
+    const size_t g = (size_t)y * N + x;
+    if constexpr (KIND == K_INIT64 || KIND == K_ITER64) {
+        double W[C], Uc[C], ukc[C];
+        if constexpr (KIND == K_INIT64) {
+            const double *src = s.src;
+            const bool prox = s.init != 0;
+            auto acc_u = [&](int c, int dy, int dx) -> double {
+                const size_t gi = (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
+                if (!prox) return src[c * NN + gi];
+                if constexpr (EQ == EQ_LAP5) return prox_ac(src[gi], s.ht, s.b);
+                else if constexpr (EQ == EQ_SCHNAK) {
+                    double u, v;
+                    prox_schnak(src[gi], src[NN + gi], s.ht, s.sa, s.sb, s.kappa, u, v);
+                    return c == 0 ? u : v;
+                } else return src[c * NN + gi];
+            };
+#pragma unroll
+            for (int c = 0; c < C; ++c) ukc[c] = src[c * NN + g];
+            eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
+            double *U0 = (double *)s.U[0];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                U0[c * NN + g] = Uc[c];
+                s.Uk[c * NN + g] = ukc[c];
+            }
+        } else {
+            const double *Un = (const double *)s.U[(it + 1) & 1];
+            auto acc_u = [&](int c, int dy, int dx) -> double {
+                return Un[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
+            };
+#pragma unroll
+            for (int c = 0; c < C; ++c) ukc[c] = s.Uk[c * NN + g];
+            eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            acc[c] += W[c] * W[c];
+            acc[C + c] += Uc[c] - ukc[c];
+            wv[c] = (T)W[c];
+        }
+    } else if constexpr (KIND == K_INNER32) {
+        const float *E = (const float *)s.U[(it + 1) & 1];
+        const float *Ub = s.Ub32;
+        auto acc_e = [&](int c, int dy, int dx) -> float {
+            return E[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
+        };
+        auto acc_ub = [&](int c, int dy, int dx) -> float {
+            return Ub[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
+        };
+        float rc[C], W[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) rc[c] = s.r32[c * NN + g];
+        eval_Ftilde<EQ>(s, acc_e, acc_ub, rc, W);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            acc[c] += (double)W[c] * (double)W[c];
+            wv[c] = (T)W[c];
+        }
+    } else {
+        // Mixed outer pass: U_new = U + e (FP64) or the initial U; r = F(U_new) in FP64.
+        double W[C], Uc[C], ukc[C];
+        if constexpr (KIND == K_OUTER_INIT) {
+            const double *src = s.src;
+            const bool prox = s.init != 0;
+            auto acc_u = [&](int c, int dy, int dx) -> double {
+                const size_t gi = (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
+                if (!prox) return src[c * NN + gi];
+                if constexpr (EQ == EQ_LAP5) return prox_ac(src[gi], s.ht, s.b);
+                else if constexpr (EQ == EQ_SCHNAK) {
+                    double u, v;
+                    prox_schnak(src[gi], src[NN + gi], s.ht, s.sa, s.sb, s.kappa, u, v);
+                    return c == 0 ? u : v;
+                } else return src[c * NN + gi];
+            };
+#pragma unroll
+            for (int c = 0; c < C; ++c) ukc[c] = src[c * NN + g];
+            eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                s.U64[0][c * NN + g] = Uc[c];
+                s.Uk[c * NN + g] = ukc[c];
+            }
+        } else {
+            const double *Ucur = s.U64[sst.outer & 1];
+            double *Unext = s.U64[(sst.outer + 1) & 1];
+            const float *E = (const float *)s.U[sst.iters & 1];
+            const bool has_e = sst.iters > 0;
+            auto acc_u = [&](int c, int dy, int dx) -> double {
+                const size_t gi = c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
+                return has_e ? Ucur[gi] + (double)E[gi] : Ucur[gi];
+            };
+#pragma unroll
+            for (int c = 0; c < C; ++c) ukc[c] = s.Uk[c * NN + g];
+            eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
+#pragma unroll
+            for (int c = 0; c < C; ++c) Unext[c * NN + g] = Uc[c];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            acc[c] += W[c] * W[c];
+            acc[C + c] += Uc[c] - ukc[c];
+            s.r32[c * NN + g] = (float)W[c];
+            s.Ub32[c * NN + g] = (float)Uc[c];
+            wv[c] = (T)(float)W[c];
+        }
     }
-    __syncthreads();
-    return skip == 0;
+}
+
+// ---------------------------------------------------------------- spectrum layout
+// Per component, N^2/2 complex entries: (kx, y) for kx < N/2 the packed row
+// spectrum slot (periodic) or cosine pair (Neumann) of row y.  Stored in tiles
+// of the row pass's R rows, S[c][y / R][kx][y % R]: a row-pass workgroup writes
+// one contiguous block, and a column-pass workgroup that takes CB adjacent
+// columns reads CB * R contiguous entries per tile.
+template <int R>
+__device__ __forceinline__ size_t spec_off(int c, int y, int kx, int N) {
+    const size_t H = (size_t)N / 2;
+    return (size_t)c * H * N + ((size_t)(y / R) * H + kx) * R + (y % R);
 }
 
 // ---------------------------------------------------------------- row pass, forward
@@ -323,183 +452,102 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
     constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
     constexpr int R = rows_per_block<T, LOGN, C>();
     constexpr int NREG = C * R / 2;
-    __shared__ cplx<T> buf[C * R * H];
+    __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
     __shared__ double scratch[2 * C * (NT / 64)];
-    __shared__ State sst;
-    const Slot &s = *slots[blockIdx.y];
-    if (!load_state<KIND>(s, sst)) return;
+    SlotRef s = slot_of(slots);
+    StateRef sst = state_of(s);
+    if (skip_launch<KIND>(sst)) return;
 
     const int y0 = blockIdx.x * R;
-    const size_t NN = (size_t)N * N;
-    const int it = sst.iters;
     double acc[2 * C];
 #pragma unroll
     for (int k = 0; k < 2 * C; ++k) acc[k] = 0.0;
 
+#pragma unroll 8
     for (int idx = threadIdx.x; idx < R * N; idx += NT) {
         const int r = idx >> LOGN, x = idx & (N - 1);
         const int y = y0 + r;
-        const size_t g = (size_t)y * N + x;
         T wv[C];
-        if constexpr (KIND == K_INIT64 || KIND == K_ITER64) {
-            double W[C], Uc[C], ukc[C];
-            if constexpr (KIND == K_INIT64) {
-                const double *src = s.src;
-                const bool prox = s.init != 0;
-                auto acc_u = [&](int c, int dy, int dx) -> double {
-                    const size_t gi = (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
-                    if (!prox) return src[c * NN + gi];
-                    if constexpr (EQ == EQ_LAP5) return prox_ac(src[gi], s.ht, s.b);
-                    else if constexpr (EQ == EQ_SCHNAK) {
-                        double u, v;
-                        prox_schnak(src[gi], src[NN + gi], s.ht, s.sa, s.sb, s.kappa, u, v);
-                        return c == 0 ? u : v;
-                    } else return src[c * NN + gi];
-                };
-#pragma unroll
-                for (int c = 0; c < C; ++c) ukc[c] = src[c * NN + g];
-                eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
-                double *U0 = (double *)s.U[0];
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    U0[c * NN + g] = Uc[c];
-                    s.Uk[c * NN + g] = ukc[c];
-                }
-            } else {
-                const double *Un = (const double *)s.U[(it + 1) & 1];
-                auto acc_u = [&](int c, int dy, int dx) -> double {
-                    return Un[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
-                };
-#pragma unroll
-                for (int c = 0; c < C; ++c) ukc[c] = s.Uk[c * NN + g];
-                eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
-            }
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                acc[c] += W[c] * W[c];
-                acc[C + c] += Uc[c] - ukc[c];
-                wv[c] = (T)W[c];
-            }
-        } else if constexpr (KIND == K_INNER32) {
-            const float *E = (const float *)s.U[(it + 1) & 1];
-            const float *Ub = s.Ub32;
-            auto acc_e = [&](int c, int dy, int dx) -> float {
-                return E[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
-            };
-            auto acc_ub = [&](int c, int dy, int dx) -> float {
-                return Ub[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
-            };
-            float rc[C], W[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) rc[c] = s.r32[c * NN + g];
-            eval_Ftilde<EQ>(s, acc_e, acc_ub, rc, W);
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                acc[c] += (double)W[c] * (double)W[c];
-                wv[c] = (T)W[c];
-            }
-        } else {
-            // Mixed outer pass: U_new = U + e (FP64) or the initial U; r = F(U_new) in FP64.
-            double W[C], Uc[C], ukc[C];
-            if constexpr (KIND == K_OUTER_INIT) {
-                const double *src = s.src;
-                const bool prox = s.init != 0;
-                auto acc_u = [&](int c, int dy, int dx) -> double {
-                    const size_t gi = (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
-                    if (!prox) return src[c * NN + gi];
-                    if constexpr (EQ == EQ_LAP5) return prox_ac(src[gi], s.ht, s.b);
-                    else if constexpr (EQ == EQ_SCHNAK) {
-                        double u, v;
-                        prox_schnak(src[gi], src[NN + gi], s.ht, s.sa, s.sb, s.kappa, u, v);
-                        return c == 0 ? u : v;
-                    } else return src[c * NN + gi];
-                };
-#pragma unroll
-                for (int c = 0; c < C; ++c) ukc[c] = src[c * NN + g];
-                eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    s.U64[0][c * NN + g] = Uc[c];
-                    s.Uk[c * NN + g] = ukc[c];
-                }
-            } else {
-                const double *Ucur = s.U64[sst.outer & 1];
-                double *Unext = s.U64[(sst.outer + 1) & 1];
-                const float *E = (const float *)s.U[sst.iters & 1];
-                const bool has_e = sst.iters > 0;
-                auto acc_u = [&](int c, int dy, int dx) -> double {
-                    const size_t gi = c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
-                    return has_e ? Ucur[gi] + (double)E[gi] : Ucur[gi];
-                };
-#pragma unroll
-                for (int c = 0; c < C; ++c) ukc[c] = s.Uk[c * NN + g];
-                eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
-#pragma unroll
-                for (int c = 0; c < C; ++c) Unext[c * NN + g] = Uc[c];
-            }
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                acc[c] += W[c] * W[c];
-                acc[C + c] += Uc[c] - ukc[c];
-                s.r32[c * NN + g] = (float)W[c];
-                s.Ub32[c * NN + g] = (float)Uc[c];
-                wv[c] = (T)(float)W[c];
-            }
-        }
+        produce_W<T, LOGN, BC, EQ, KIND>(s, sst, y, x, wv, acc);
         const int pos = (BC == BC_P) ? x : dct_pos(x, N);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            T *reg = reinterpret_cast<T *>(buf + (c * R / 2 + r / 2) * N);
-            reg[2 * pos + (r & 1)] = wv[c];
-        }
+        for (int c = 0; c < C; ++c) rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = wv[c];
     }
     __syncthreads();
     const cplx<T> *tw = (const cplx<T> *)s.tw;
     const cplx<T> *twd = (const cplx<T> *)s.twd;
-    wg_fft<T, LOGN, -1, NREG>(buf, tw);
-    rows_post_forward<T, LOGN, BC, NREG>(buf, twd);
-    // Transposed store: S[c][kx][y0 + r] = buf[c][r][kx]; R consecutive rows per kx.
+    wg_fft16<T, LOGN, -1, NREG, NT>(buf, tw);
+    rows_post_forward<T, LOGN, BC, NREG, NT>(buf, twd);
+    // Tile store: this workgroup's R rows are one contiguous block per component.
     cplx<T> *S = (cplx<T> *)s.S;
+#pragma unroll 8
     for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
         const int r = idx % R, rest = idx / R;
         const int kx = rest % H, c = rest / H;
-        S[((size_t)c * H + kx) * N + y0 + r] = buf[(c * R + r) * H + kx];
+        S[spec_off<R>(c, y0 + r, kx, N)] = buf[rix<LOGN>(c * R / 2 + r / 2, (r & 1) * H + kx)];
     }
-    reduce_and_finalize<KIND, C>(s, acc, scratch);
+    write_partials<C>(s, acc, scratch);
 }
 
 // ---------------------------------------------------------------- column pass
+// A workgroup takes CB adjacent columns of one component, one transform per
+// N/16 threads.  CB is chosen so that the CB x R block of a spectrum tile it
+// reads is at least 128 bytes (and the workgroup at least one wave), as far as
+// 96 KB of LDS and 1024 threads allow.
+template <typename T, int LOGN, int C> constexpr int col_jobs() {
+    constexpr int N = 1 << LOGN;
+    constexpr int R = rows_per_block<T, LOGN, C>();
+    constexpr int tile_bytes = R * (int)sizeof(cplx<T>);
+    constexpr int by_tile = tile_bytes >= 128 ? 1 : 128 / tile_bytes;
+    constexpr int by_wave = (N / 16 >= 64) ? 1 : 64 / (N / 16);
+    constexpr int want = by_tile > by_wave ? by_tile : by_wave;
+    // LDS (<= 96 KB) and threads (<= 1024) bound it from above
+    constexpr int by_lds = 98304 / (lds_region<LOGN>() * (int)sizeof(cplx<T>));
+    constexpr int by_thr = 1024 / (N / 16 >= 1 ? N / 16 : 1);
+    constexpr int cap = by_lds < by_thr ? by_lds : by_thr;
+    constexpr int cb0 = want < cap ? want : cap;
+    constexpr int cb1 = cb0 < 1 ? 1 : (cb0 > N / 2 ? N / 2 : cb0);
+    // a power of two, so that it divides N/2
+    return cb1 >= 16 ? 16 : cb1 >= 8 ? 8 : cb1 >= 4 ? 4 : cb1 >= 2 ? 2 : 1;
+}
+template <typename T, int LOGN, int C> constexpr int col_threads() { return col_jobs<T, LOGN, C>() * ((1 << LOGN) / 16); }
+
 template <typename T, int LOGN, int BC, int C>
-__global__ __launch_bounds__(NT) void k_cols(Slot *const *slots) {
+__global__ __launch_bounds__((col_threads<T, LOGN, C>())) void k_cols(Slot *const *slots) {
     constexpr int N = 1 << LOGN, H = N / 2;
-    constexpr int CB = NT / fft_team<LOGN>();   // column jobs per workgroup
-    __shared__ cplx<T> buf[CB * N];
-    __shared__ State sst;
-    const Slot &s = *slots[blockIdx.y];
-    if (!load_state<K_ITER64>(s, sst)) return;
-    const int njobs_total = C * H;
-    const int job0 = blockIdx.x * CB;
-    const int njobs = min(CB, njobs_total - job0);
+    constexpr int NTH = col_threads<T, LOGN, C>();
+    constexpr int CB = col_jobs<T, LOGN, C>();
+    constexpr int R = rows_per_block<T, LOGN, C>();
+    __shared__ cplx<T> buf[CB * lds_region<LOGN>()];
+    SlotRef s = slot_of(slots);
+    StateRef sst = state_of(s);
+    if (skip_launch<K_ITER64>(sst)) return;
+    // blockIdx.x -> (component, first column); CB divides N/2
+    const int c = blockIdx.x / (H / CB);
+    const int kx0 = (blockIdx.x % (H / CB)) * CB;
     cplx<T> *S = (cplx<T> *)s.S;
-    for (int idx = threadIdx.x; idx < CB * N; idx += NT) {
-        const int reg = idx >> LOGN, y = idx & (N - 1);
-        if (reg < njobs) {
-            const int pos = (BC == BC_P) ? y : dct_pos(y, N);
-            buf[reg * N + pos] = S[(size_t)(job0 + reg) * N + y];
-        }
+    // consecutive threads: rows of a tile, then columns, then tiles
+#pragma unroll 8
+    for (int idx = threadIdx.x; idx < CB * N; idx += NTH) {
+        const int r = idx % R, rest = idx / R;
+        const int reg = rest % CB, yt = rest / CB;
+        const int y = yt * R + r;
+        const int pos = (BC == BC_P) ? y : dct_pos(y, N);
+        buf[rix<LOGN>(reg, pos)] = S[spec_off<R>(c, y, kx0 + reg, N)];
     }
     __syncthreads();
     const cplx<T> *tw = (const cplx<T> *)s.tw;
     const cplx<T> *twd = (const cplx<T> *)s.twd;
-    wg_fft<T, LOGN, -1, CB>(buf, tw);
-    cols_apply_symbol<T, LOGN, BC, CB>(buf, job0, njobs, s, twd);
-    wg_fft<T, LOGN, +1, CB>(buf, tw);
-    for (int idx = threadIdx.x; idx < CB * N; idx += NT) {
-        const int reg = idx >> LOGN, y = idx & (N - 1);
-        if (reg < njobs) {
-            const int pos = (BC == BC_P) ? y : dct_pos(y, N);
-            S[(size_t)(job0 + reg) * N + y] = buf[reg * N + pos];
-        }
+    wg_fft16<T, LOGN, -1, CB, NTH>(buf, tw);
+    cols_apply_symbol<T, LOGN, BC, CB, NTH>(buf, c * H + kx0, CB, s, twd);
+    wg_fft16<T, LOGN, +1, CB, NTH>(buf, tw);
+#pragma unroll 8
+    for (int idx = threadIdx.x; idx < CB * N; idx += NTH) {
+        const int r = idx % R, rest = idx / R;
+        const int reg = rest % CB, yt = rest / CB;
+        const int y = yt * R + r;
+        const int pos = (BC == BC_P) ? y : dct_pos(y, N);
+        S[spec_off<R>(c, y, kx0 + reg, N)] = buf[rix<LOGN>(reg, pos)];
     }
 }
 
@@ -509,32 +557,34 @@ __global__ __launch_bounds__(NT) void k_rowinv(Slot *const *slots) {
     constexpr int N = 1 << LOGN, H = N / 2;
     constexpr int R = rows_per_block<T, LOGN, C>();
     constexpr int NREG = C * R / 2;
-    __shared__ cplx<T> buf[C * R * H];
-    __shared__ State sst;
-    const Slot &s = *slots[blockIdx.y];
-    if (!load_state<K_ITER64>(s, sst)) return;
+    __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
+    SlotRef s = slot_of(slots);
+    StateRef sst = state_of(s);
+    if (skip_launch<K_ITER64>(sst)) return;
     const int y0 = blockIdx.x * R;
     const size_t NN = (size_t)N * N;
     const cplx<T> *S = (const cplx<T> *)s.S;
+#pragma unroll 8
     for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
         const int r = idx % R, rest = idx / R;
         const int kx = rest % H, c = rest / H;
-        buf[(c * R + r) * H + kx] = S[((size_t)c * H + kx) * N + y0 + r];
+        buf[rix<LOGN>(c * R / 2 + r / 2, (r & 1) * H + kx)] = S[spec_off<R>(c, y0 + r, kx, N)];
     }
     __syncthreads();
     const cplx<T> *tw = (const cplx<T> *)s.tw;
     const cplx<T> *twd = (const cplx<T> *)s.twd;
-    rows_pre_inverse<T, LOGN, BC, NREG>(buf, twd);
-    wg_fft<T, LOGN, +1, NREG>(buf, tw);
+    rows_pre_inverse<T, LOGN, BC, NREG, NT>(buf, twd);
+    wg_fft16<T, LOGN, +1, NREG, NT>(buf, tw);
     T *P = (T *)s.P;
     T *Pt = (T *)s.Pt;
     const T tp = (T)s.tau_p, om = (T)s.omega;
     const bool first = sst.iters == 0;
+#pragma unroll 8
     for (int idx = threadIdx.x; idx < C * R * N; idx += NT) {
         const int x = idx & (N - 1), rest = idx >> LOGN;
         const int r = rest % R, c = rest / R;
         const int pos = (BC == BC_P) ? x : dct_pos(x, N);
-        const cplx<T> zv = buf[(c * R / 2 + r / 2) * N + pos];
+        const cplx<T> zv = buf[rix<LOGN>(c * R / 2 + r / 2, pos)];
         const T Y = (r & 1) ? zv.im : zv.re;
         const size_t g = c * NN + (size_t)(y0 + r) * N + x;
         const T Pn = first ? (T)0 : P[g];
@@ -545,39 +595,62 @@ __global__ __launch_bounds__(NT) void k_rowinv(Slot *const *slots) {
 }
 
 // ---------------------------------------------------------------- primal update
+// Each thread updates UPD_PPT consecutive points of one row.
+constexpr int UPD_PPT = 4;
+
 template <typename T, int LOGN, int BC, int EQ, int MODE>
 __global__ __launch_bounds__(NT) void k_upd(Slot *const *slots) {
     constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
     constexpr int N = 1 << LOGN;
     constexpr size_t NN = (size_t)N * N;
-    __shared__ State sst;
-    const Slot &s = *slots[blockIdx.y];
-    if (!load_state<K_ITER64>(s, sst)) return;
-    const size_t g = (size_t)blockIdx.x * NT + threadIdx.x;
-    if (g >= NN) return;
-    const int y = (int)(g >> LOGN), x = (int)(g & (N - 1));
+    SlotRef s = slot_of(slots);
+    StateRef sst = state_of(s);
+    if (skip_launch<K_ITER64>(sst)) return;
+    const size_t g0 = ((size_t)blockIdx.x * NT + threadIdx.x) * UPD_PPT;
+    if (g0 >= NN) return;
     const int it = sst.iters;
-    const T *Pt = (const T *)s.Pt;
-    auto acc_p = [&](int c, int dy, int dx) -> T {
-        return Pt[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
-    };
-    T *Unext = (T *)s.U[(it + 1) & 1];
-    const T *Ucur = (const T *)s.U[it & 1];
-    T un[C], Uc[C], adj[C];
+    const auto Pt = gp((const T *)s.Pt);
+    const auto Unext = gp((T *)s.U[(it + 1) & 1]);
+    const auto Ucur = gp((const T *)s.U[it & 1]);
+    const auto Ub = gp((const float *)s.Ub32);
+    const T tu = (T)s.tau_u;
+    // All loads of the thread's points first, then compute and store, so that the
+    // stores cannot serialise the next point's loads.
+    T pst[UPD_PPT][C][13], un[UPD_PPT][C], Uc[UPD_PPT][C];
+    constexpr int NP = EQ == EQ_BIH ? 13 : 5;
+    constexpr int DY[13] = {0, 0, 0, -1, 1, -1, -1, 1, 1, 0, 0, -2, 2};
+    constexpr int DX[13] = {0, -1, 1, 0, 0, -1, 1, -1, 1, -2, 2, 0, 0};
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        if constexpr (MODE == MODE_F64) {
-            un[c] = Ucur[c * NN + g];
-            Uc[c] = un[c];
-        } else {
-            un[c] = it == 0 ? (T)0 : Ucur[c * NN + g];
-            Uc[c] = s.Ub32[c * NN + g] + un[c];
+    for (int k = 0; k < UPD_PPT; ++k) {
+        const size_t g = g0 + k;
+        const int y = (int)(g >> LOGN), x = (int)(g & (N - 1));
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+                pst[k][c][q] = Pt[c * NN + (size_t)wrap<BC>(y + DY[q], N) * N + wrap<BC>(x + DX[q], N)];
+            if constexpr (MODE == MODE_F64) {
+                un[k][c] = Ucur[c * NN + g];
+                Uc[k][c] = un[k][c];
+            } else {
+                un[k][c] = it == 0 ? (T)0 : Ucur[c * NN + g];
+                Uc[k][c] = (T)Ub[c * NN + g] + un[k][c];
+            }
         }
     }
-    eval_adjoint<EQ, T>(s, acc_p, Uc, adj);
-    const T tu = (T)s.tau_u;
 #pragma unroll
-    for (int c = 0; c < C; ++c) Unext[c * NN + g] = un[c] - tu * adj[c];
+    for (int k = 0; k < UPD_PPT; ++k) {
+        auto acc_p = [&](int c, int dy, int dx) -> T {
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+                if (DY[q] == dy && DX[q] == dx) return pst[k][c][q];
+            return (T)0;
+        };
+        T adj[C];
+        eval_adjoint<EQ, T>(s, acc_p, Uc[k], adj);
+#pragma unroll
+        for (int c = 0; c < C; ++c) Unext[c * NN + g0 + k] = un[k][c] - tu * adj[c];
+    }
 }
 
 // ---------------------------------------------------------------- kernel-level entry points
@@ -587,7 +660,7 @@ __global__ __launch_bounds__(NT) void k_residual(const Slot *sp, const double *U
                                                  double *partials) {
     constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
     __shared__ double scratch[C * (NT / 64)];
-    const Slot &s = *sp;
+    SlotRef s = slot_ref(sp);
     const int N = s.N;
     const size_t NN = (size_t)N * N;
     const size_t g = (size_t)blockIdx.x * NT + threadIdx.x;
@@ -619,7 +692,7 @@ __global__ __launch_bounds__(NT) void k_residual(const Slot *sp, const double *U
 // Pointwise reaction prox of every grid point.
 template <int EQ>
 __global__ __launch_bounds__(NT) void k_prox(const Slot *sp, const double *cin, double *uout) {
-    const Slot &s = *sp;
+    SlotRef s = slot_ref(sp);
     const size_t NN = (size_t)s.N * s.N;
     const size_t g = (size_t)blockIdx.x * NT + threadIdx.x;
     if (g >= NN) return;
@@ -643,25 +716,26 @@ __global__ __launch_bounds__(NT) void k_rows_transform_in(Slot *const *slots, co
     constexpr int N = 1 << LOGN, H = N / 2;
     constexpr int R = rows_per_block<T, LOGN, C>();
     constexpr int NREG = C * R / 2;
-    __shared__ cplx<T> buf[C * R * H];
-    const Slot &s = *slots[blockIdx.y];
+    __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
+    SlotRef s = slot_of(slots);
     const int y0 = blockIdx.x * R;
     const size_t NN = (size_t)N * N;
+#pragma unroll 8
     for (int idx = threadIdx.x; idx < C * R * N; idx += NT) {
         const int x = idx & (N - 1), rest = idx >> LOGN;
         const int r = rest % R, c = rest / R;
         const int pos = (BC == BC_P) ? x : dct_pos(x, N);
-        T *reg = reinterpret_cast<T *>(buf + (c * R / 2 + r / 2) * N);
-        reg[2 * pos + (r & 1)] = (T)W[c * NN + (size_t)(y0 + r) * N + x];
+        rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = (T)W[c * NN + (size_t)(y0 + r) * N + x];
     }
     __syncthreads();
-    wg_fft<T, LOGN, -1, NREG>(buf, (const cplx<T> *)s.tw);
-    rows_post_forward<T, LOGN, BC, NREG>(buf, (const cplx<T> *)s.twd);
+    wg_fft16<T, LOGN, -1, NREG, NT>(buf, (const cplx<T> *)s.tw);
+    rows_post_forward<T, LOGN, BC, NREG, NT>(buf, (const cplx<T> *)s.twd);
     cplx<T> *S = (cplx<T> *)s.S;
+#pragma unroll 8
     for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
         const int r = idx % R, rest = idx / R;
         const int kx = rest % H, c = rest / H;
-        S[((size_t)c * H + kx) * N + y0 + r] = buf[(c * R + r) * H + kx];
+        S[spec_off<R>(c, y0 + r, kx, N)] = buf[rix<LOGN>(c * R / 2 + r / 2, (r & 1) * H + kx)];
     }
 }
 
@@ -670,24 +744,26 @@ __global__ __launch_bounds__(NT) void k_rows_transform_out(Slot *const *slots, d
     constexpr int N = 1 << LOGN, H = N / 2;
     constexpr int R = rows_per_block<T, LOGN, C>();
     constexpr int NREG = C * R / 2;
-    __shared__ cplx<T> buf[C * R * H];
-    const Slot &s = *slots[blockIdx.y];
+    __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
+    SlotRef s = slot_of(slots);
     const int y0 = blockIdx.x * R;
     const size_t NN = (size_t)N * N;
     const cplx<T> *S = (const cplx<T> *)s.S;
+#pragma unroll 8
     for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
         const int r = idx % R, rest = idx / R;
         const int kx = rest % H, c = rest / H;
-        buf[(c * R + r) * H + kx] = S[((size_t)c * H + kx) * N + y0 + r];
+        buf[rix<LOGN>(c * R / 2 + r / 2, (r & 1) * H + kx)] = S[spec_off<R>(c, y0 + r, kx, N)];
     }
     __syncthreads();
-    rows_pre_inverse<T, LOGN, BC, NREG>(buf, (const cplx<T> *)s.twd);
-    wg_fft<T, LOGN, +1, NREG>(buf, (const cplx<T> *)s.tw);
+    rows_pre_inverse<T, LOGN, BC, NREG, NT>(buf, (const cplx<T> *)s.twd);
+    wg_fft16<T, LOGN, +1, NREG, NT>(buf, (const cplx<T> *)s.tw);
+#pragma unroll 8
     for (int idx = threadIdx.x; idx < C * R * N; idx += NT) {
         const int x = idx & (N - 1), rest = idx >> LOGN;
         const int r = rest % R, c = rest / R;
         const int pos = (BC == BC_P) ? x : dct_pos(x, N);
-        const cplx<T> zv = buf[(c * R / 2 + r / 2) * N + pos];
+        const cplx<T> zv = buf[rix<LOGN>(c * R / 2 + r / 2, pos)];
         Y[c * NN + (size_t)(y0 + r) * N + x] = (double)((r & 1) ? zv.im : zv.re);
     }
 }

@@ -75,6 +75,27 @@ struct Slot {
     State *st;
 };
 
+// ---------------------------------------------------------------- address spaces
+// Slots and their States are read through the constant address space: the
+// fields are uniform across a workgroup, so they become scalar loads.  A kernel
+// never writes the slot it reads this way (State is written only by thread 0 of
+// k_finalize, through a plain pointer), and scalar caches are invalidated at
+// every kernel start, so the values seen are those of the previous launch.
+typedef const __attribute__((address_space(4))) Slot &SlotRef;
+typedef const __attribute__((address_space(4))) State &StateRef;
+__device__ __forceinline__ SlotRef slot_ref(const Slot *p) {
+    return *(const __attribute__((address_space(4))) Slot *)p;
+}
+__device__ __forceinline__ SlotRef slot_of(Slot *const *slots) { return slot_ref(slots[blockIdx.y]); }
+__device__ __forceinline__ StateRef state_of(SlotRef s) {
+    return *(const __attribute__((address_space(4))) State *)s.st;
+}
+
+// Buffers are addressed through the global address space: pointers loaded from
+// memory are otherwise generic, and generic (flat) accesses are slower.
+template <typename T> using gptr_t = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gptr_t<T> gp(T *p) { return (gptr_t<T>)p; }
+
 // ---------------------------------------------------------------- small helpers
 template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
@@ -100,23 +121,18 @@ template <int BC> __device__ __forceinline__ int wrap(int i, int N) {
 // x = 2n -> n, x = 2n + 1 -> N - 1 - n.
 __device__ __forceinline__ int dct_pos(int x, int N) { return (x & 1) ? (N - 1 - (x >> 1)) : (x >> 1); }
 
-// Rows of the grid one row-pass workgroup owns: as many as fit ~64 KB of LDS
-// for the transform buffer (ncomp * R * N reals), at least 2 (a row pair), at
-// most 64 and at most N/4 (so that every grid spans at least four workgroups).
+// Rows of the grid one row-pass workgroup owns.  The workgroup's NT threads
+// form NT / (N/16) transform teams (one transform per N/16 threads); a row
+// pair is one transform, so R = 2 * teams keeps every team busy (R N = 32 NT
+// reals of LDS per component).  At least 2, at most N/4 (so that every grid
+// spans at least four workgroups), and for two components at most half that.
 template <typename T, int LOGN, int C> constexpr int rows_per_block() {
     constexpr int N = 1 << LOGN;
-    constexpr int fit = 65536 / (C * N * (int)sizeof(T));
-    constexpr int cap = N / 4 < 64 ? N / 4 : 64;
-    constexpr int r = fit < 2 ? 2 : (fit > cap ? cap : fit);
-    // round down to a power of two
-    return r >= 64 ? 64 : r >= 32 ? 32 : r >= 16 ? 16 : r >= 8 ? 8 : r >= 4 ? 4 : 2;
-}
-
-// FFT team: threads cooperating on one length-N transform (one radix-8
-// butterfly each); a workgroup runs NT / team transforms side by side.
-template <int LOGN> constexpr int fft_team() {
-    constexpr int n8 = (1 << LOGN) / 8;
-    return n8 < NT ? n8 : NT;
+    constexpr int teams = (N / 16 >= NT) ? 1 : NT / (N / 16);
+    constexpr int want = 2 * teams / C;
+    constexpr int cap = N / 4;
+    constexpr int r = want < 2 ? 2 : (want > cap ? cap : want);
+    return r;
 }
 
 }  // namespace rdk

@@ -49,7 +49,8 @@ def compare_fp64(ctx, rd, cfg, U0, steps, tol=None, init="prev"):
         Ug, info = ctx.step(Ug, cfg["ht"], p, o)
         assert info["status"] == "ok", (k, info)
         assert info["iters"] == r.iters, (k, info, r.iters, r.residual)
-        assert info["residual"] == pytest.approx(r.residual, rel=1e-6, abs=1e-3 * (tol or cfg["tol"]))
+        # The reported norm is a round-off-level quantity near the tolerance: agree loosely.
+        assert info["residual"] == pytest.approx(r.residual, rel=1e-3, abs=1e-2 * (tol or cfg["tol"]))
         err = max_abs(Ug.cpu().numpy(), r.U)
         assert err <= 1e-10, (k, err)
         U = r.U

@@ -102,6 +102,80 @@ def cpu_oracle_sample(cfg, u0_np):
                           "workload tolerance" % (N, N, r.iters))
 
 
+def serve_stream(ctx, rd, torch, reqs, rate):
+    """Serve the request stream: trajectory i's step j arrives at reqs[i]["arrivals"][j]
+    (seconds after the start; all zero = closed loop).  A step's latency is its
+    completion time minus max(arrival, completion of the trajectory's previous step).
+    Trajectories are opened at their first arrival and closed after their last step."""
+    n = len(reqs)
+    u0s = [torch.tensor(r["u0"], dtype=torch.float64, device="cuda") for r in reqs]
+    probs = [rd.problem_from_config(r["cfg"]) for r in reqs]
+    opts = [rd.make_opts(tol=r["cfg"]["tol"], tau_u=r["cfg"]["tau"], tau_p=r["cfg"]["tau"], omega=r["cfg"]["omega"],
+                         precision="mixed") for r in reqs]
+    torch.cuda.synchronize()
+    events = sorted((a, i, j) for i, r in enumerate(reqs) for j, a in enumerate(r["arrivals"]))
+    trajs = [None] * n
+    tickets = {}                      # ticket -> (i, j)
+    done_at = {}                      # (i, j) -> completion time
+    infos = {}
+    ev = 0
+    t0 = time.perf_counter()
+    total = len(events)
+    while len(done_at) < total:
+        now = time.perf_counter() - t0
+        while ev < total and events[ev][0] <= now:
+            _, i, j = events[ev]
+            if trajs[i] is None:
+                trajs[i] = ctx.open(probs[i], opts[i], u0s[i])
+            tickets[trajs[i].submit(reqs[i]["cfg"]["ht"])] = (i, j)
+            ev += 1
+        ctx.pump()
+        now = time.perf_counter() - t0
+        for tk, (i, j) in list(tickets.items()):
+            info = ctx.poll(tk)
+            if info is None:
+                continue
+            del tickets[tk]
+            done_at[(i, j)] = now
+            infos[(i, j)] = info
+            if j == len(reqs[i]["arrivals"]) - 1:
+                trajs[i].close()
+        if ev < total and not tickets:
+            time.sleep(max(0.0, min(1e-3, events[ev][0] - now)))
+    wall = time.perf_counter() - t0
+    lat = []
+    pts = 0
+    statuses = {}
+    for (i, j), t in done_at.items():
+        start = reqs[i]["arrivals"][j]
+        if j > 0:
+            start = max(start, done_at[(i, j - 1)])
+        lat.append(t - start)
+        N = reqs[i]["cfg"]["N"]
+        pts += N * N * infos[(i, j)]["iters"]
+        st = infos[(i, j)]["status"]
+        statuses[st] = statuses.get(st, 0) + 1
+    return dict(requests=total, wall_s=wall, req_per_s=total / wall, pt_iters_per_s=pts / wall,
+                p50_ms=1e3 * percentile(lat, 50), p99_ms=1e3 * percentile(lat, 99), status=statuses,
+                rate_req_per_s=rate)
+
+
+def serving_leg(rd, torch, wl, n_traj, steps_per_traj):
+    """Mixed-precision serving stream: closed-loop pass for the saturation rate,
+    then Poisson arrivals at 0.7 x that rate."""
+    ctx = rd.Context(0)
+    try:
+        closed = serve_stream(ctx, rd, torch, wl.serving_requests(n_traj, steps_per_traj, seed=5), None)
+        rate = 0.7 * closed["req_per_s"]
+        opened = serve_stream(ctx, rd, torch, wl.serving_requests(n_traj, steps_per_traj, seed=5, rate=rate), rate)
+    finally:
+        ctx.close()
+    return dict(closed_loop=closed, poisson=opened,
+                stream="%d trajectories x %d steps, Allen-Cahn / Cahn-Hilliard / Schnakenberg uniform, N in "
+                       "{64..1024}, periodic/Neumann 50/50, h_t log-uniform [1e-4, 1e-2], FP32-mixed"
+                       % (n_traj, steps_per_traj))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +184,9 @@ def main():
     ap.add_argument("--workload", default="ac2048")
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel for the HIP-event timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream leg")
+    ap.add_argument("--serve-traj", type=int, default=64, help="trajectories in the serving stream")
+    ap.add_argument("--serve-steps", type=int, default=8, help="steps per trajectory in the serving stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -150,6 +227,12 @@ def main():
                     frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
                     bytes_per_launch=dk["bytes"], ms_per_launch=dk["ms"])
 
+    serving = None
+    if not args.no_serve:
+        log("serving stream: %d trajectories x %d steps" % (args.serve_traj, args.serve_steps))
+        serving = serving_leg(rd, torch, wl, args.serve_traj, args.serve_steps)
+        log("  %s" % json.dumps(serving))
+
     accuracy = {}
     cpu = None
     if not args.no_cpu:
@@ -171,7 +254,7 @@ def main():
         "p50_ms": mx["p50_ms"], "p99_ms": mx["p99_ms"],
         "mixed": mx, "fp64": f64,
         "speedup_mixed_vs_fp64": f64["wall_s"] / mx["wall_s"],
-        "accuracy": accuracy, "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu,
+        "accuracy": accuracy, "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu, "serving": serving,
     }
     ctx.close()
     print(json.dumps(line), flush=True)

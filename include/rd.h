@@ -153,25 +153,51 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
                                const double *u_n, int32_t reps, void *hip_stream, double *ms_out);
 
 /* ---- serving: continuous batching of steps of resident trajectories ----------------- */
-/* Set the device-memory budget for resident trajectories (bytes; 0 = unlimited).         */
+/* A trajectory keeps U^k and, once admitted, its whole step workspace resident in device
+ * memory.  Each pump round admits queued trajectories (arrival order, while the budget
+ * allows), starts the next submitted step of every idle admitted trajectory, and
+ * advances every running step by one round of iterations.  Running steps that share
+ * (precision, N, boundary condition, equation family) form a batch group: one launch
+ * per kernel covers all of them (one workgroup row per step), and different groups run
+ * on separate streams so that they overlap on the device.  A step's arithmetic does not
+ * depend on what else is in the batch: each result equals the one rd_step returns.
+ * Serving calls synchronise their own streams and ignore hip_stream ordering of other
+ * work except where noted.                                                               */
+
+/* Set the device-memory budget for admitted trajectories (bytes; 0 = unlimited).  A
+ * trajectory is admitted while resident + its workspace <= budget, and always when
+ * nothing is resident (so a single request larger than the budget still runs).        */
 rd_status rd_serve_set_budget(void *ctx, size_t bytes);
-/* Open a trajectory: copies u0 (DEVICE) to resident state.  Does not reserve memory yet:
- * it is admitted (memory reserved) by rd_serve_pump when the budget allows.              */
+/* Open a trajectory: copies u0 (DEVICE, [c][N][N] FP64) into a resident copy, ordered
+ * after prior work on hip_stream, and synchronises it.  *out (HOST) receives the handle.
+ * Workspace memory is reserved only at admission, by rd_serve_pump.                    */
 rd_status rd_traj_open(void *ctx, const rd_problem *prob, const rd_opts *opts,
                        const double *u0, void *hip_stream, void **out);
 /* Queue one implicit step of size h_t; *ticket (HOST) identifies it.  Steps of one
- * trajectory run in submission order.                                                     */
+ * trajectory run in submission order, each starting from the previous one's result.    */
 rd_status rd_traj_submit(void *traj, double h_t, uint64_t *ticket);
-/* Admit queued work as budget and slots allow, advance every running step by one batched
- * launch round, retire finished steps.  Returns after one round (or max_wait_us).         */
+/* One serving round (admit, start, advance, retire).  max_wait_us is reserved and must
+ * be >= 0; the call returns after one round.                                              */
 rd_status rd_serve_pump(void *ctx, int32_t max_wait_us);
-/* RD_E_BUSY until the ticket's step finished; then fills info (HOST) and returns its
- * status.                                                                                 */
+/* RD_E_BUSY until the ticket's step finished; then fills info (HOST) and returns the
+ * step's status.  RD_E_INVALID for an unknown ticket.                                   */
 rd_status rd_poll(void *ctx, uint64_t ticket, rd_info *info);
-/* Copy the trajectory's current state to u_out (DEVICE).  Synchronises.                   */
+/* Copy the trajectory's current state U^k to u_out (DEVICE).  Synchronises.            */
 rd_status rd_traj_read(void *traj, double *u_out, void *hip_stream);
-/* Close a trajectory and release its resident memory.                                    */
+/* Close a trajectory: waits for the device, releases its workspace (returning its bytes
+ * to the budget) and its resident state.  Unfinished tickets of it stay RD_E_BUSY.      */
 rd_status rd_traj_close(void *traj);
+
+typedef struct {
+    uint64_t budget_bytes;   /* as set by rd_serve_set_budget                              */
+    uint64_t resident_bytes; /* workspace bytes of admitted trajectories                   */
+    int32_t admitted;        /* trajectories holding a workspace                           */
+    int32_t queued;          /* trajectories waiting for admission                         */
+    int32_t running;         /* steps in progress                                          */
+    int32_t pending_steps;   /* submitted steps not started yet                            */
+} rd_serve_info;
+/* Snapshot of the serving state (HOST out).  Host-only; no device work.                */
+rd_status rd_serve_stats(void *ctx, rd_serve_info *out);
 
 const char *rd_status_str(rd_status s);
 

@@ -243,8 +243,14 @@ __device__ __forceinline__ void finalize(SlotRef s, const double *sumsq, const d
             st->status = ST_NONFINITE;
             st->outer_done = 1;
             st->done = 1;
-        } else if (res <= st->inner_target || it >= s.max_iter) {
-            st->done = 1;
+        } else {
+            int best_it = st->inner_best_it;
+            if (res < INNER_DROP * st->inner_best) {
+                st->inner_best = res;
+                best_it = it;
+                st->inner_best_it = it;
+            }
+            if (res <= st->inner_target || it >= s.max_iter || it - best_it >= INNER_STALL) st->done = 1;
         }
     } else {
         int outer = 0;
@@ -268,8 +274,9 @@ __device__ __forceinline__ void finalize(SlotRef s, const double *sumsq, const d
         st->done = odone;
         st->iters = 0;
         st->inner_target = s.inner_rtol * res;
+        st->inner_best = res;
+        st->inner_best_it = 0;
     }
-    st->counter = 0u;
     __threadfence();
 }
 

@@ -30,8 +30,8 @@ constexpr double GROWTH_LIMIT = 1e8;    // residual growth that counts as diverg
 
 template <typename T> struct cplx { T re, im; };
 
-// Per-slot iteration state, written only by the last workgroup of a
-// residual kernel (fixed-order reduction) and read at the start of every kernel.
+// Per-slot iteration state, written only by k_finalize (after the fixed-order
+// reduction of a residual pass) and read at the start of every kernel.
 struct State {
     int done;          // inner loop finished (FP64 path: the whole step)
     int iters;         // iterations of the current (inner) PDHG loop
@@ -39,7 +39,7 @@ struct State {
     int outer;         // mixed: outer passes completed
     int outer_done;    // mixed: step finished
     int status;        // ST_*
-    unsigned counter;  // arrival counter for the last-block reduction
+    int inner_best_it; // mixed: inner iteration of the last 10% drop of the inner norm
     int pad;
     double res;        // latest ||F/h_t|| of the current loop (FP64 path: paper norm)
     double res0;       // paper norm at U_0
@@ -47,7 +47,14 @@ struct State {
     double inner_target;
     double mass;       // sum(U - U^k) at the latest FP64 residual evaluation
     double inner_res;
+    double inner_best; // mixed: inner norm at inner_best_it
 };
+
+// The inner FP32 loop also ends when its norm has not dropped by INNER_DROP for
+// INNER_STALL iterations: it has reached the FP32 round-off floor of F~, and
+// further iterations cannot help the outer FP64 correction.
+constexpr int INNER_STALL = 32;
+constexpr double INNER_DROP = 0.9;
 
 struct Slot {
     int N, ncomp, bc, eq;

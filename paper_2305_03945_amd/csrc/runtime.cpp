@@ -156,7 +156,13 @@ struct Ctx {
     std::map<uint64_t, Ticket> tickets;
     std::vector<Traj *> trajs;
     std::deque<Traj *> admit_queue;
+    // one stream per concurrently advanced batch group (default priority)
+    std::vector<hipStream_t> serve_streams;
 };
+
+// Batch groups advanced in one pump round run on separate streams, so that
+// groups of different shapes overlap on the device.
+constexpr int SERVE_STREAMS = 4;
 
 struct PendingStep {
     uint64_t ticket;
@@ -173,6 +179,7 @@ struct Traj {
     std::deque<PendingStep> pending;
     bool running = false;
     uint64_t running_ticket = 0;
+    int issued = 0;                      // iterations launched for the running step
     bool queued_for_admission = false;
 };
 
@@ -525,6 +532,7 @@ rd_status rd_destroy(void *ctx) {
             (void)hipFree(kv.second.twd[i]);
         }
     }
+    for (hipStream_t q : c->serve_streams) (void)hipStreamDestroy(q);
     if (c->scratch_slot_dev) (void)hipFree(c->scratch_slot_dev);
     if (c->scratch_slot_host) (void)hipHostFree(c->scratch_slot_host);
     if (c->scratch_partials) (void)hipFree(c->scratch_partials);
@@ -607,7 +615,6 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
     run.done = 0;
     run.outer_done = 0;
     run.iters = 1;
-    run.counter = 0;
     if (run.res0 == 0.0) run.res0 = 1.0;
     *w->st_host = run;
     launch_fn fns[4] = {k.cols, k.rowinv, k.upd, k.rowfwd};
@@ -804,10 +811,14 @@ struct BatchBuffers {
     Slot **host = nullptr;
     int cap = 0;
 };
-std::map<Ctx *, std::map<GroupKey, BatchBuffers>> g_batch;
+// Device slot-pointer lists per (context, group, role): role 0 for the init
+// launch of starting steps, role 1 for the iteration round.  A list is rewritten
+// only in a later pump round, after the stream that read it was synchronised.
+std::map<Ctx *, std::map<std::pair<GroupKey, int>, BatchBuffers>> g_batch;
 
-rd_status batch_list(Ctx *c, const GroupKey &key, const std::vector<Traj *> &ts, Slot **&dev, hipStream_t st) {
-    BatchBuffers &b = g_batch[c][key];
+rd_status batch_list(Ctx *c, const GroupKey &key, int role, const std::vector<Traj *> &ts, Slot **&dev,
+                     hipStream_t st) {
+    BatchBuffers &b = g_batch[c][std::make_pair(key, role)];
     const int n = (int)ts.size();
     if (b.cap < n) {
         if (b.dev) (void)hipFree(b.dev);
@@ -831,13 +842,16 @@ rd_status batch_list(Ctx *c, const GroupKey &key, const std::vector<Traj *> &ts,
 extern "C" {
 
 rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
-    (void)max_wait_us;
-    if (!ctx) return RD_E_INVALID;
+    if (!ctx || max_wait_us < 0) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
     RD_CHECK(hipSetDevice(c->device));
-    hipStream_t st = nullptr;
+    while ((int)c->serve_streams.size() < SERVE_STREAMS) {
+        hipStream_t q = nullptr;
+        RD_CHECK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        c->serve_streams.push_back(q);
+    }
     rd_status r;
-    // 1. admission
+    // 1. admission, in arrival order, while the resident budget allows
     while (!c->admit_queue.empty()) {
         Traj *t = c->admit_queue.front();
         const size_t need = workspace_bytes(t->d.N, t->d.C, t->d.mode,
@@ -852,56 +866,71 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
         c->admit_queue.pop_front();
         t->queued_for_admission = false;
     }
-    // 2. start pending steps, 3. advance, per key
+    // 2. group admitted trajectories; take the next pending step of idle ones
     std::map<GroupKey, std::vector<Traj *>> starting, running;
     for (Traj *t : c->trajs) {
         if (!t->ws) continue;
         GroupKey key{t->d.mode, t->d.logN, t->d.bc, t->d.eq};
         if (!t->running && !t->pending.empty()) {
-            PendingStep ps = t->pending.front();
-            t->pending.pop_front();
-            Tables *tb = nullptr;
-            if ((r = get_tables(c, t->d.N, t->d.bc, t->d.h, tb)) != RD_OK) return r;
-            Slot &s = *t->ws->slot_host;
-            std::memset(&s, 0, sizeof(Slot));
-            fill_params(s, &t->prob, &t->opts, t->d, ps.ht);
-            bind_workspace(s, *t->ws, *tb);
-            s.src = t->u;
-            RD_CHECK(hipMemcpyAsync(t->ws->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
-            t->running = true;
-            t->running_ticket = ps.ticket;
             starting[key].push_back(t);
+            running[key].push_back(t);
+        } else if (t->running) {
+            running[key].push_back(t);
         }
-        if (t->running) running[key].push_back(t);
     }
-    for (auto &kv : starting) {
-        Slot **dev = nullptr;
-        if ((r = batch_list(c, kv.first, kv.second, dev, st)) != RD_OK) return r;
-        g_kernels[kv.first.mode][kv.first.logN][kv.first.bc][kv.first.eq].init(dev, (int)kv.second.size(), st);
-        RD_CHECK(hipGetLastError());
-        // the list buffer is reused below: wait for the init launch to consume it
-        RD_CHECK(hipStreamSynchronize(st));
-    }
+    // 3. per group, on its own stream: upload the slots of starting steps, one
+    //    batched init launch, one batched round of iterations, state readback
+    std::map<GroupKey, hipStream_t> gstream;
+    int gi = 0;
     for (auto &kv : running) {
         const GroupKey &key = kv.first;
+        hipStream_t st = c->serve_streams[gi++ % SERVE_STREAMS];
+        gstream[key] = st;
+        const KSet &k = g_kernels[key.mode][key.logN][key.bc][key.eq];
+        auto si = starting.find(key);
+        if (si != starting.end()) {
+            for (Traj *t : si->second) {
+                PendingStep ps = t->pending.front();
+                t->pending.pop_front();
+                Tables *tb = nullptr;
+                if ((r = get_tables(c, t->d.N, t->d.bc, t->d.h, tb)) != RD_OK) return r;
+                Slot &s = *t->ws->slot_host;
+                std::memset(&s, 0, sizeof(Slot));
+                fill_params(s, &t->prob, &t->opts, t->d, ps.ht);
+                bind_workspace(s, *t->ws, *tb);
+                s.src = t->u;
+                RD_CHECK(hipMemcpyAsync(t->ws->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
+                t->running = true;
+                t->running_ticket = ps.ticket;
+                t->issued = 0;
+            }
+            Slot **dev = nullptr;
+            if ((r = batch_list(c, key, 0, si->second, dev, st)) != RD_OK) return r;
+            k.init(dev, (int)si->second.size(), st);
+            RD_CHECK(hipGetLastError());
+        }
         Slot **dev = nullptr;
-        if ((r = batch_list(c, key, kv.second, dev, st)) != RD_OK) return r;
+        if ((r = batch_list(c, key, 1, kv.second, dev, st)) != RD_OK) return r;
+        // Round length: the trajectory's previous step predicts this one; a step
+        // that runs longer grows its rounds geometrically (fewer host round trips).
         int iters = 0;
         for (Traj *t : kv.second) {
             const Workspace &w = *t->ws;
-            iters = std::max(iters, key.mode == MODE_F64 ? (w.last_iters > 0 ? w.last_iters + 1 : 8)
-                                                         : (w.last_inner > 0 ? w.last_inner + 1 : 6));
+            const int pred = key.mode == MODE_F64 ? (w.last_iters > 0 ? w.last_iters + 1 : 8)
+                                                  : (w.last_inner > 0 ? w.last_inner + 1 : 6);
+            iters = std::max(iters, std::max(pred, t->issued / 2));
         }
         iters = std::min(iters, 64);
-        enqueue_round(g_kernels[key.mode][key.logN][key.bc][key.eq], key.mode, dev, (int)kv.second.size(), iters, 1,
-                      st);
+        for (Traj *t : kv.second) t->issued += iters;
+        enqueue_round(k, key.mode, dev, (int)kv.second.size(), iters, 1, st);
         RD_CHECK(hipGetLastError());
         for (Traj *t : kv.second)
             RD_CHECK(hipMemcpyAsync(t->ws->st_host, t->ws->proto.st, sizeof(State), hipMemcpyDeviceToHost, st));
-        RD_CHECK(hipStreamSynchronize(st));
     }
-    // 4. retire
+    for (auto &kv : gstream) RD_CHECK(hipStreamSynchronize(kv.second));
+    // 4. retire finished steps: U^{k+1} becomes the resident state
     for (auto &kv : running) {
+        hipStream_t st = gstream[kv.first];
         for (Traj *t : kv.second) {
             Workspace &w = *t->ws;
             const State &s = *w.st_host;
@@ -920,7 +949,22 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
             t->running = false;
         }
     }
-    RD_CHECK(hipStreamSynchronize(st));
+    for (auto &kv : gstream) RD_CHECK(hipStreamSynchronize(kv.second));
+    return RD_OK;
+}
+
+rd_status rd_serve_stats(void *ctx, rd_serve_info *out) {
+    if (!ctx || !out) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    std::memset(out, 0, sizeof(*out));
+    out->budget_bytes = c->budget;
+    out->resident_bytes = c->resident;
+    for (Traj *t : c->trajs) {
+        if (t->ws) ++out->admitted;
+        if (t->running) ++out->running;
+        out->pending_steps += (int32_t)t->pending.size();
+    }
+    out->queued = (int32_t)c->admit_queue.size();
     return RD_OK;
 }
 

@@ -30,7 +30,7 @@ STATUS_NAMES = {RD_OK: "ok", RD_E_INVALID: "invalid", RD_E_NOCONV: "noconv", RD_
 # Every C-ABI symbol include/rd.h declares.
 EXPORTED = ("rd_create", "rd_destroy", "rd_default_opts", "rd_footprint_bytes", "rd_step", "rd_residual",
             "rd_precond_solve", "rd_prox", "rd_profile_iteration", "rd_serve_set_budget", "rd_traj_open", "rd_traj_submit",
-            "rd_serve_pump", "rd_poll", "rd_traj_read", "rd_traj_close", "rd_status_str")
+            "rd_serve_pump", "rd_poll", "rd_traj_read", "rd_traj_close", "rd_serve_stats", "rd_status_str")
 
 
 class Problem(ctypes.Structure):
@@ -56,6 +56,14 @@ class Info(ctypes.Structure):
                     status_code=self.status)
 
 
+class ServeInfo(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("resident_bytes", ctypes.c_uint64), ("admitted", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("running", ctypes.c_int32), ("pending_steps", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _P = ctypes.POINTER
 _sig = {
@@ -76,6 +84,7 @@ _sig = {
     "rd_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _P(Info)]),
     "rd_traj_read": (ctypes.c_int, [_vp, _vp, _vp]),
     "rd_traj_close": (ctypes.c_int, [_vp]),
+    "rd_serve_stats": (ctypes.c_int, [_vp, _P(ServeInfo)]),
     "rd_status_str": (ctypes.c_char_p, [ctypes.c_int]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -234,6 +243,11 @@ class Context:
 
     def pump(self, max_wait_us=0):
         _check(_lib.rd_serve_pump(self._h, int(max_wait_us)), "rd_serve_pump")
+
+    def serve_stats(self):
+        out = ServeInfo()
+        _check(_lib.rd_serve_stats(self._h, ctypes.byref(out)), "rd_serve_stats")
+        return out.as_dict()
 
     def poll(self, ticket):
         info = Info()

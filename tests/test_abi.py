@@ -1,0 +1,118 @@
+"""CPU checks of the C ABI: the library loads, exports every function include/rd.h
+declares, its structs have the header's layout, and the host-only entry points
+behave as documented.  No device work is requested."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rd_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def rd():
+    from paper_2305_03945_amd import rd as rdmod
+    return rdmod
+
+
+def test_library_exports_every_declared_function(rd):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(rd._lib, n), n
+    assert sorted(rd.EXPORTED) == names
+
+
+def test_struct_layout_matches_header(rd):
+    """Compile the header with the host C compiler and compare sizes and offsets."""
+    fields = {
+        "rd_problem": (rd.Problem, ["nx", "ny", "lx", "ly", "bc", "op", "rx", "pad0", "diff", "p"]),
+        "rd_opts": (rd.Opts, ["tol", "max_iter", "max_outer", "tau_u", "tau_p", "omega", "precision", "init",
+                              "inner_rtol"]),
+        "rd_info": (rd.Info, ["iters", "outer", "residual_l2", "residual0", "mass_drift", "status", "pad0"]),
+        "rd_serve_info": (rd.ServeInfo, ["budget_bytes", "resident_bytes", "admitted", "queued", "running",
+                                         "pending_steps"]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rd.h"', "int main(void) {"]
+    for st, (_, fl) in fields.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (st, st))
+        for f in fl:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (st, f, st, f))
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            a, b, c = ln.split()
+            got[(a, b)] = int(c)
+    for st, (cls, fl) in fields.items():
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for f in fl:
+            assert got[(st, f)] == getattr(cls, f).offset, (st, f)
+
+
+def test_default_opts_and_status_strings(rd):
+    o = rd.Opts()
+    rd._lib.rd_default_opts(ctypes.byref(o))
+    assert (o.tol, o.max_iter, o.max_outer, o.tau_u, o.tau_p, o.omega) == (1e-10, 10000, 20, 0.9, 0.9, 1.0)
+    assert (o.precision, o.init, o.inner_rtol) == (rd.RD_FP64, rd.RD_INIT_PREV, 1e-3)
+    for code in (rd.RD_OK, rd.RD_E_INVALID, rd.RD_E_NOCONV, rd.RD_E_NONFINITE, rd.RD_E_NOMEM, rd.RD_E_DEVICE,
+                 rd.RD_E_BUSY):
+        s = rd.status_str(code)
+        assert s and s != "unknown status"
+    assert rd.status_str(17) == "unknown status"
+
+
+def test_footprint_is_host_logic_and_validates(rd):
+    o64 = rd.make_opts(precision="fp64")
+    omx = rd.make_opts(precision="mixed")
+    p = rd.make_problem("allen_cahn", 256, diff=(1e-4,))
+    a, b = rd.footprint_bytes(p, o64), rd.footprint_bytes(p, omx)
+    # FP64: U[2], P, Pt, S, U^k and the resident state = 7 fields of 8 bytes per point at least
+    assert a >= 7 * 8 * 256 * 256
+    # mixed: 7 FP32 fields + 4 FP64 fields (U64[2], U^k, resident state)
+    assert b >= (7 * 4 + 4 * 8) * 256 * 256
+    s = rd.make_problem("schnakenberg", 256, diff=(1.0, 10.0), a=0.1, sb=0.9, kappa=1.0)
+    assert rd.footprint_bytes(s, o64) >= 2 * 7 * 8 * 256 * 256
+    for bad in (rd.make_problem("allen_cahn", 100), rd.make_problem("allen_cahn", 8192),
+                rd.make_problem("allen_cahn", 8)):
+        assert rd.footprint_bytes(bad, o64) == 0
+    badopt = rd.make_opts(tau_u=-1.0)
+    assert rd.footprint_bytes(p, badopt) == 0
+
+
+def test_create_without_a_device_fails_loudly(rd):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert rd._lib.rd_create(0, ctypes.byref(h)) == rd.RD_E_DEVICE
+    with pytest.raises(rd.RDError):
+        rd.Context(0)
+
+
+def test_null_handles_are_rejected(rd):
+    info = rd.Info()
+    assert rd._lib.rd_destroy(None) == rd.RD_E_INVALID
+    assert rd._lib.rd_serve_pump(None, 0) == rd.RD_E_INVALID
+    assert rd._lib.rd_poll(None, 1, ctypes.byref(info)) == rd.RD_E_INVALID
+    assert rd._lib.rd_traj_close(None) == rd.RD_E_INVALID
+    assert rd._lib.rd_serve_stats(None, None) == rd.RD_E_INVALID
+    p = rd.make_problem("allen_cahn", 64)
+    o = rd.make_opts()
+    assert rd._lib.rd_step(None, ctypes.byref(p), ctypes.byref(o), 1e-3, None, None, None,
+                           ctypes.byref(info)) == rd.RD_E_INVALID

@@ -1,0 +1,219 @@
+"""GPU tests of the serving loop (continuous batching of resident trajectories).
+
+A step's arithmetic does not depend on the batch it runs in: every result from the
+mix must equal, bitwise, the result of the same steps run alone through rd_step,
+and the iteration counts and statuses must agree.  Admission must respect the
+device-memory budget, and trajectories opened while others run must be admitted as
+memory frees up.
+"""
+import numpy as np
+import pytest
+
+from paper_2305_03945_amd import workloads as wl
+from tests.rd_cases import max_abs, oracle_opts, oracle_problem, small_cfg
+
+pytestmark = pytest.mark.gpu
+
+MAX_PUMPS = 20000
+
+
+@pytest.fixture(scope="module")
+def rd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_03945_amd import rd as rdmod
+    return rdmod
+
+
+def dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def request(kind, N, bc, precision, seed, hts):
+    cfg = small_cfg(kind, N, bc)
+    return dict(cfg=cfg, precision=precision, u0=wl.initial_field(cfg, N=N, seed=seed), hts=list(hts))
+
+
+def opts_for(rd, cfg, precision):
+    return rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], omega=cfg["omega"],
+                        precision=precision)
+
+
+def run_alone(rd, req):
+    """The same steps, one rd_step call after another, on a fresh context."""
+    ctx = rd.Context(0)
+    try:
+        p = rd.problem_from_config(req["cfg"])
+        o = opts_for(rd, req["cfg"], req["precision"])
+        u = dev(req["u0"])
+        infos = []
+        for ht in req["hts"]:
+            u, info = ctx.step(u, ht, p, o)
+            infos.append(info)
+        return u.cpu().numpy(), infos
+    finally:
+        ctx.close()
+
+
+def pump_until(ctx, done, on_round=None):
+    for n in range(MAX_PUMPS):
+        if done():
+            return n
+        ctx.pump()
+        if on_round is not None:
+            on_round(n)
+    raise AssertionError("serving did not finish within %d pump rounds" % MAX_PUMPS)
+
+
+MIX = [
+    ("allen_cahn", 64, "periodic", "mixed", 11, (1e-3, 2e-3, 1e-3)),
+    ("allen_cahn", 64, "periodic", "mixed", 12, (5e-3, 1e-3)),          # same group as the first
+    ("allen_cahn", 128, "neumann", "fp64", 13, (1e-3, 1e-3)),
+    ("cahn_hilliard", 64, "neumann", "mixed", 14, (1e-4, 5e-5, 1e-4)),
+    ("cahn_hilliard", 32, "periodic", "fp64", 15, (1e-4,)),
+    ("schnakenberg", 128, "periodic", "mixed", 16, (1e-3, 2e-3)),
+    ("schnakenberg", 64, "neumann", "fp64", 17, (1e-3,)),
+]
+
+
+def test_results_in_the_mix_equal_results_alone(rd):
+    reqs = [request(*m) for m in MIX]
+    ctx = rd.Context(0)
+    try:
+        trajs, tickets = [], []
+        for r in reqs:
+            t = ctx.open(rd.problem_from_config(r["cfg"]), opts_for(rd, r["cfg"], r["precision"]), dev(r["u0"]))
+            trajs.append(t)
+            tickets.append([t.submit(ht) for ht in r["hts"]])
+        infos = {}
+
+        def all_done():
+            for tl in tickets:
+                for tk in tl:
+                    if tk not in infos:
+                        i = ctx.poll(tk)
+                        if i is not None:
+                            infos[tk] = i
+            return len(infos) == sum(len(tl) for tl in tickets)
+
+        pump_until(ctx, all_done)
+        for r, t, tl in zip(reqs, trajs, tickets):
+            alone, alone_infos = run_alone(rd, r)
+            mixed = t.read().cpu().numpy()
+            assert np.array_equal(mixed, alone), (r["cfg"]["kind"], r["cfg"]["N"], max_abs(mixed, alone))
+            for tk, ai in zip(tl, alone_infos):
+                si = infos[tk]
+                assert (si["iters"], si["outer"], si["status"]) == (ai["iters"], ai["outer"], ai["status"]), (si, ai)
+                assert si["residual"] == ai["residual"]
+            t.close()
+    finally:
+        ctx.close()
+
+
+def test_mixed_serving_result_matches_oracle(rd):
+    """One served Allen-Cahn step against the FP64 oracle, at the mixed path's 1e-5."""
+    from oracle import pdhg as opdhg
+    req = request("allen_cahn", 64, "periodic", "mixed", 21, (1e-3,))
+    cfg = req["cfg"]
+    ctx = rd.Context(0)
+    try:
+        t = ctx.open(rd.problem_from_config(cfg), opts_for(rd, cfg, "mixed"), dev(req["u0"]))
+        tk = t.submit(req["hts"][0])
+        pump_until(ctx, lambda: ctx.poll(tk) is not None)
+        got = t.read().cpu().numpy()
+        ref = opdhg.step(oracle_problem(cfg), req["u0"], req["hts"][0], oracle_opts(cfg, tol=1e-10))
+        assert max_abs(got, ref.U) <= 1e-5
+        t.close()
+    finally:
+        ctx.close()
+
+
+def test_budget_bounds_admission_and_queued_work_completes(rd):
+    """Five trajectories, a budget that holds two workspaces: never more than two
+    admitted, and closing finished trajectories lets the queued ones in."""
+    reqs = [request("allen_cahn", 128, "periodic", "mixed", 30 + i, (1e-3, 1e-3)) for i in range(5)]
+    ctx = rd.Context(0)
+    try:
+        cfg = reqs[0]["cfg"]
+        p = rd.problem_from_config(cfg)
+        o = opts_for(rd, cfg, "mixed")
+        fp = rd.footprint_bytes(p, o)
+        assert fp > 0
+        ctx.set_budget(2 * fp)
+        trajs = [ctx.open(p, o, dev(r["u0"])) for r in reqs]
+        tickets = [[t.submit(ht) for ht in r["hts"]] for t, r in zip(trajs, reqs)]
+        results = [None] * len(reqs)
+        seen_admitted = []
+
+        def check(_):
+            st = ctx.serve_stats()
+            assert st["resident_bytes"] <= st["budget_bytes"]
+            assert st["admitted"] <= 2
+            seen_admitted.append(st["admitted"])
+            for i, t in enumerate(trajs):
+                if t is not None and all(ctx.poll(tk) is not None for tk in tickets[i]):
+                    results[i] = t.read().cpu().numpy()
+                    t.close()
+                    trajs[i] = None
+
+        pump_until(ctx, lambda: all(r is not None for r in results), on_round=check)
+        assert max(seen_admitted) == 2
+        st = ctx.serve_stats()
+        assert st["admitted"] == 0 and st["queued"] == 0 and st["resident_bytes"] == 0
+        for r, res in zip(reqs, results):
+            alone, _ = run_alone(rd, r)
+            assert np.array_equal(res, alone)
+    finally:
+        ctx.close()
+
+
+def test_late_arrivals_join_running_batches(rd):
+    """Requests submitted while others are mid-step start at the next round and
+    finish with the same result as alone (continuous batching, not a queue)."""
+    first = request("allen_cahn", 64, "periodic", "fp64", 41, (1e-3, 1e-3, 1e-3))
+    late = [request("allen_cahn", 64, "periodic", "fp64", 42, (2e-3,)),
+            request("schnakenberg", 64, "periodic", "mixed", 43, (1e-3,))]
+    ctx = rd.Context(0)
+    try:
+        t0 = ctx.open(rd.problem_from_config(first["cfg"]), opts_for(rd, first["cfg"], "fp64"), dev(first["u0"]))
+        tk0 = [t0.submit(ht) for ht in first["hts"]]
+        ctx.pump()
+        st = ctx.serve_stats()
+        assert st["admitted"] == 1 and st["queued"] == 0
+        late_t, late_tk = [], []
+        for r in late:
+            t = ctx.open(rd.problem_from_config(r["cfg"]), opts_for(rd, r["cfg"], r["precision"]), dev(r["u0"]))
+            late_t.append(t)
+            late_tk.append([t.submit(ht) for ht in r["hts"]])
+        ctx.pump()
+        st = ctx.serve_stats()
+        # the late requests were admitted and started while the first one still had work
+        assert st["admitted"] == 3
+        assert any(ctx.poll(tk) is None for tk in tk0)
+        pump_until(ctx, lambda: all(ctx.poll(tk) is not None for tl in [tk0] + late_tk for tk in tl))
+        for r, t in zip([first] + late, [t0] + late_t):
+            alone, _ = run_alone(rd, r)
+            assert np.array_equal(t.read().cpu().numpy(), alone)
+            t.close()
+    finally:
+        ctx.close()
+
+
+def test_poll_and_argument_errors(rd):
+    ctx = rd.Context(0)
+    try:
+        with pytest.raises(rd.RDError):
+            ctx.poll(123456789)
+        with pytest.raises(rd.RDError):
+            ctx.pump(-1)
+        cfg = small_cfg("allen_cahn", 64, "periodic")
+        t = ctx.open(rd.problem_from_config(cfg), opts_for(rd, cfg, "fp64"), dev(wl.initial_field(cfg, N=64)))
+        with pytest.raises(rd.RDError):
+            t.submit(0.0)
+        with pytest.raises(rd.RDError):
+            t.submit(float("nan"))
+        t.close()
+    finally:
+        ctx.close()

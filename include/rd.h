@@ -143,12 +143,13 @@ rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *c
                   void *hip_stream);
 
 /* ---- instrumentation ------------------------------------------------------------- */
-/* Time the four kernels of one Algorithm-1 iteration in isolation on hip_stream:
- * prepares the step for u_n (DEVICE) like rd_step, then launches each kernel `reps`
- * times, each launch bracketed by its own pair of HIP events on that stream, with the
- * slot's iteration state reset before every launch.  ms_out (HOST, 4 doubles) receives
- * the mean launch durations in milliseconds of: column pass, inverse row pass + dual
- * update, primal update, residual + forward row pass.  Synchronises.                    */
+/* Time the four kernels of one Algorithm-1 iteration on hip_stream: prepares the step
+ * for u_n (DEVICE) like rd_step (stop test disabled), then for each kernel resets the
+ * slot's iteration state, launches it once untimed and `reps` times back to back
+ * between one pair of HIP events on that stream.  ms_out (HOST, 4 doubles) receives
+ * the mean time per launch in milliseconds (kernel plus the dispatch gap between
+ * dependent launches) of: column pass, inverse row pass + dual update, primal update,
+ * residual + forward row pass (with its stop-decision kernel).  Synchronises.            */
 rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
                                const double *u_n, int32_t reps, void *hip_stream, double *ms_out);
 

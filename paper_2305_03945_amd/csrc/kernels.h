@@ -164,6 +164,46 @@ __device__ __forceinline__ void eval_adjoint(SlotRef s, Acc p, const V *Uc, V *o
     }
 }
 
+// ---------------------------------------------------------------- stencil windows
+// Four consecutive points (y, x0 .. x0+3) of one row, x0 a multiple of 4, with
+// the stencil neighbourhood they need: row y + dy holds x0 - hx .. x0 + 3 + hx,
+// hx = HY - |dy| (HY = 1: the 5-point stencil; HY = 2: the 13-point one; HY = 0:
+// the four points only).  The four middle values are one aligned vector load;
+// the edge values are scalar loads through the boundary map.
+template <typename T> using vec4_t = T __attribute__((ext_vector_type(4)));
+
+template <typename T, int HY> struct Win {
+    T v[2 * HY + 1][4 + 2 * HY];
+    __device__ __forceinline__ T at(int k, int dy, int dx) const { return v[dy + HY][HY + dx + k]; }
+};
+
+template <typename T, int BC, int LOGN, int HY>
+__device__ __forceinline__ void load_win(Win<T, HY> &w, gptr_t<const T> f, int y, int x0) {
+    constexpr int N = 1 << LOGN;
+#pragma unroll
+    for (int dy = -HY; dy <= HY; ++dy) {
+        const int hx = HY - (dy < 0 ? -dy : dy);
+        const gptr_t<const T> row = f + (size_t)wrap<BC>(y + dy, N) * N;
+        const vec4_t<T> m = *(const gptr_t<const vec4_t<T>>)(row + x0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w.v[dy + HY][HY + k] = m[k];
+#pragma unroll
+        for (int h = 1; h <= hx; ++h) {
+            w.v[dy + HY][HY - h] = row[wrap<BC>(x0 - h, N)];
+            w.v[dy + HY][HY + 3 + h] = row[wrap<BC>(x0 + 3 + h, N)];
+        }
+    }
+}
+
+template <typename T> __device__ __forceinline__ vec4_t<T> load4(gptr_t<const T> p) {
+    return *(const gptr_t<const vec4_t<T>>)p;
+}
+template <typename T> __device__ __forceinline__ void store4(gptr_t<T> p, const vec4_t<T> &v) {
+    *(gptr_t<vec4_t<T>>)p = v;
+}
+
+template <int EQ> constexpr int stencil_hy() { return EQ == EQ_BIH ? 2 : 1; }
+
 // ---------------------------------------------------------------- deterministic block sums
 template <int K> __device__ __forceinline__ void block_sum(double *v, double *scratch /* K * NT/64 */) {
 #pragma unroll
@@ -284,11 +324,11 @@ __device__ __forceinline__ void finalize(SlotRef s, const double *sumsq, const d
 // per component) to the slot's partials array.  The stop decision is taken by
 // k_finalize, launched right after, which reads them after the kernel boundary.
 template <int C>
-__device__ __forceinline__ void write_partials(SlotRef s, double *acc /* 2C */, double *scratch) {
+__device__ __forceinline__ void write_partials(SlotRef s, int tile, double *acc /* 2C */, double *scratch) {
     block_sum<2 * C>(acc, scratch);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < 2 * C; ++k) s.partials[blockIdx.x * (2 * C) + k] = acc[k];
+        for (int k = 0; k < 2 * C; ++k) s.partials[tile * (2 * C) + k] = acc[k];
     }
 }
 
@@ -308,8 +348,8 @@ template <int KIND, int C>
 __global__ __launch_bounds__(NT) void k_finalize(Slot *const *slots) {
     __shared__ double scratch[2 * C * (NT / 64)];
     SlotRef s = slot_of(slots);
-    StateRef sst = state_of(s);
-    if (skip_launch<KIND>(sst)) return;
+    // The partial sums are loaded before the state is tested, so that the two
+    // memory latencies overlap (reading them is harmless when the launch skips).
     double v[2 * C];
 #pragma unroll
     for (int k = 0; k < 2 * C; ++k) v[k] = 0.0;
@@ -317,6 +357,8 @@ __global__ __launch_bounds__(NT) void k_finalize(Slot *const *slots) {
 #pragma unroll
         for (int k = 0; k < 2 * C; ++k) v[k] += s.partials[bl * (2 * C) + k];
     }
+    StateRef sst = state_of(s);
+    if (skip_launch<KIND>(sst)) return;
     block_sum<2 * C>(v, scratch);
     if (threadIdx.x == 0) finalize<KIND, C>(s, v, v + C);
 }
@@ -440,6 +482,71 @@ __device__ __forceinline__ void produce_W(SlotRef s, StateRef sst, int y, int x,
     }
 }
 
+// The same for the two iteration kinds, on four consecutive points (y, x0..x0+3)
+// with vector loads: wv[k][c] receives W at point k.
+template <typename T, int LOGN, int BC, int EQ, int KIND>
+__device__ __forceinline__ void produce_W4(SlotRef s, StateRef sst, int y, int x0, T (*wv)[EQ == EQ_SCHNAK ? 2 : 1],
+                                           double *acc) {
+    constexpr int N = 1 << LOGN;
+    constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
+    constexpr size_t NN = (size_t)N * N;
+    constexpr int HY = stencil_hy<EQ>();
+    const int it = sst.iters;
+    const size_t g0 = (size_t)y * N + x0;
+    if constexpr (KIND == K_ITER64) {
+        const auto Un = gp((const double *)s.U[(it + 1) & 1]);
+        Win<double, HY> wu[C];
+        vec4_t<double> uk[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            load_win<double, BC, LOGN, HY>(wu[c], Un + c * NN, y, x0);
+            uk[c] = load4<double>(gp((const double *)s.Uk) + c * NN + g0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double W[C], Uc[C], ukc[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) ukc[c] = uk[c][k];
+            eval_F<EQ, double>(s, [&](int c, int dy, int dx) { return wu[c].at(k, dy, dx); }, ukc, W, Uc);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                acc[c] += W[c] * W[c];
+                acc[C + c] += Uc[c] - ukc[c];
+                wv[k][c] = (T)W[c];
+            }
+        }
+    } else {
+        static_assert(KIND == K_INNER32, "vectorised producer: iteration kinds only");
+        // Cahn-Hilliard needs U at the 5-point neighbours (reaction under Lap);
+        // the others only at the point.
+        constexpr int HU = EQ == EQ_BIH ? 1 : 0;
+        const auto E = gp((const float *)s.U[(it + 1) & 1]);
+        const auto Ub = gp((const float *)s.Ub32);
+        Win<float, HY> we[C];
+        Win<float, HU> wub[C];
+        vec4_t<float> r4[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            load_win<float, BC, LOGN, HY>(we[c], E + c * NN, y, x0);
+            load_win<float, BC, LOGN, HU>(wub[c], Ub + c * NN, y, x0);
+            r4[c] = load4<float>(gp((const float *)s.r32) + c * NN + g0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float rc[C], W[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) rc[c] = r4[c][k];
+            eval_Ftilde<EQ>(s, [&](int c, int dy, int dx) { return we[c].at(k, dy, dx); },
+                            [&](int c, int dy, int dx) { return wub[c].at(k, dy, dx); }, rc, W);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                acc[c] += (double)W[c] * (double)W[c];
+                wv[k][c] = (T)W[c];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- spectrum layout
 // Per component, N^2/2 complex entries: (kx, y) for kx < N/2 the packed row
 // spectrum slot (periodic) or cosine pair (Neumann) of row y.  Stored in tiles
@@ -465,20 +572,37 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
     StateRef sst = state_of(s);
     if (skip_launch<KIND>(sst)) return;
 
-    const int y0 = blockIdx.x * R;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int y0 = tile * R;
     double acc[2 * C];
 #pragma unroll
     for (int k = 0; k < 2 * C; ++k) acc[k] = 0.0;
 
-#pragma unroll 8
-    for (int idx = threadIdx.x; idx < R * N; idx += NT) {
-        const int r = idx >> LOGN, x = idx & (N - 1);
-        const int y = y0 + r;
-        T wv[C];
-        produce_W<T, LOGN, BC, EQ, KIND>(s, sst, y, x, wv, acc);
-        const int pos = (BC == BC_P) ? x : dct_pos(x, N);
+    if constexpr (KIND == K_ITER64 || KIND == K_INNER32) {
+        // four consecutive points per thread and pass, vector loads
+#pragma unroll 2
+        for (int idx = threadIdx.x; idx < R * N / 4; idx += NT) {
+            const int r = idx >> (LOGN - 2), x0 = (idx & (N / 4 - 1)) * 4;
+            T wv[4][C];
+            produce_W4<T, LOGN, BC, EQ, KIND>(s, sst, y0 + r, x0, wv, acc);
 #pragma unroll
-        for (int c = 0; c < C; ++c) rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = wv[c];
+            for (int k = 0; k < 4; ++k) {
+                const int pos = (BC == BC_P) ? x0 + k : dct_pos(x0 + k, N);
+#pragma unroll
+                for (int c = 0; c < C; ++c) rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = wv[k][c];
+            }
+        }
+    } else {
+#pragma unroll 8
+        for (int idx = threadIdx.x; idx < R * N; idx += NT) {
+            const int r = idx >> LOGN, x = idx & (N - 1);
+            const int y = y0 + r;
+            T wv[C];
+            produce_W<T, LOGN, BC, EQ, KIND>(s, sst, y, x, wv, acc);
+            const int pos = (BC == BC_P) ? x : dct_pos(x, N);
+#pragma unroll
+            for (int c = 0; c < C; ++c) rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = wv[c];
+        }
     }
     __syncthreads();
     const cplx<T> *tw = (const cplx<T> *)s.tw;
@@ -493,7 +617,7 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
         const int kx = rest % H, c = rest / H;
         S[spec_off<R>(c, y0 + r, kx, N)] = buf[rix<LOGN>(c * R / 2 + r / 2, (r & 1) * H + kx)];
     }
-    write_partials<C>(s, acc, scratch);
+    write_partials<C>(s, tile, acc, scratch);
 }
 
 // ---------------------------------------------------------------- column pass
@@ -602,7 +726,7 @@ __global__ __launch_bounds__(NT) void k_rowinv(Slot *const *slots) {
 }
 
 // ---------------------------------------------------------------- primal update
-// Each thread updates UPD_PPT consecutive points of one row.
+// Each thread updates UPD_PPT = 4 consecutive points of one row.
 constexpr int UPD_PPT = 4;
 
 template <typename T, int LOGN, int BC, int EQ, int MODE>
@@ -610,54 +734,51 @@ __global__ __launch_bounds__(NT) void k_upd(Slot *const *slots) {
     constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
     constexpr int N = 1 << LOGN;
     constexpr size_t NN = (size_t)N * N;
+    constexpr int HY = stencil_hy<EQ>();
     SlotRef s = slot_of(slots);
     StateRef sst = state_of(s);
     if (skip_launch<K_ITER64>(sst)) return;
-    const size_t g0 = ((size_t)blockIdx.x * NT + threadIdx.x) * UPD_PPT;
+    const size_t g0 = ((size_t)xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x) * UPD_PPT;
     if (g0 >= NN) return;
+    const int y = (int)(g0 >> LOGN), x0 = (int)(g0 & (N - 1));
     const int it = sst.iters;
     const auto Pt = gp((const T *)s.Pt);
-    const auto Unext = gp((T *)s.U[(it + 1) & 1]);
     const auto Ucur = gp((const T *)s.U[it & 1]);
-    const auto Ub = gp((const float *)s.Ub32);
-    const T tu = (T)s.tau_u;
-    // All loads of the thread's points first, then compute and store, so that the
-    // stores cannot serialise the next point's loads.
-    T pst[UPD_PPT][C][13], un[UPD_PPT][C], Uc[UPD_PPT][C];
-    constexpr int NP = EQ == EQ_BIH ? 13 : 5;
-    constexpr int DY[13] = {0, 0, 0, -1, 1, -1, -1, 1, 1, 0, 0, -2, 2};
-    constexpr int DX[13] = {0, -1, 1, 0, 0, -1, 1, -1, 1, -2, 2, 0, 0};
+    const auto Unext = gp((T *)s.U[(it + 1) & 1]);
+    Win<T, HY> wp[C];
+    vec4_t<T> un[C];
+    T Uc[UPD_PPT][C];
 #pragma unroll
-    for (int k = 0; k < UPD_PPT; ++k) {
-        const size_t g = g0 + k;
-        const int y = (int)(g >> LOGN), x = (int)(g & (N - 1));
+    for (int c = 0; c < C; ++c) {
+        load_win<T, BC, LOGN, HY>(wp[c], Pt + c * NN, y, x0);
+        if constexpr (MODE == MODE_F64) {
+            un[c] = load4<T>(Ucur + c * NN + g0);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
+            for (int k = 0; k < UPD_PPT; ++k) Uc[k][c] = un[c][k];
+        } else {
+            // mixed: the iterate is the correction e (e_0 = 0); f' is taken at U + e
+            if (it == 0) {
 #pragma unroll
-            for (int q = 0; q < NP; ++q)
-                pst[k][c][q] = Pt[c * NN + (size_t)wrap<BC>(y + DY[q], N) * N + wrap<BC>(x + DX[q], N)];
-            if constexpr (MODE == MODE_F64) {
-                un[k][c] = Ucur[c * NN + g];
-                Uc[k][c] = un[k][c];
+                for (int k = 0; k < UPD_PPT; ++k) un[c][k] = (T)0;
             } else {
-                un[k][c] = it == 0 ? (T)0 : Ucur[c * NN + g];
-                Uc[k][c] = (T)Ub[c * NN + g] + un[k][c];
+                un[c] = load4<T>(Ucur + c * NN + g0);
             }
+            const vec4_t<float> ub = load4<float>(gp((const float *)s.Ub32) + c * NN + g0);
+#pragma unroll
+            for (int k = 0; k < UPD_PPT; ++k) Uc[k][c] = (T)ub[k] + un[c][k];
         }
     }
+    const T tu = (T)s.tau_u;
+    vec4_t<T> out[C];
 #pragma unroll
     for (int k = 0; k < UPD_PPT; ++k) {
-        auto acc_p = [&](int c, int dy, int dx) -> T {
-#pragma unroll
-            for (int q = 0; q < NP; ++q)
-                if (DY[q] == dy && DX[q] == dx) return pst[k][c][q];
-            return (T)0;
-        };
         T adj[C];
-        eval_adjoint<EQ, T>(s, acc_p, Uc[k], adj);
+        eval_adjoint<EQ, T>(s, [&](int c, int dy, int dx) { return wp[c].at(k, dy, dx); }, Uc[k], adj);
 #pragma unroll
-        for (int c = 0; c < C; ++c) Unext[c * NN + g0 + k] = un[k][c] - tu * adj[c];
+        for (int c = 0; c < C; ++c) out[c][k] = un[c][k] - tu * adj[c];
     }
+#pragma unroll
+    for (int c = 0; c < C; ++c) store4<T>(Unext + c * NN + g0, out[c]);
 }
 
 // ---------------------------------------------------------------- kernel-level entry points

@@ -103,6 +103,17 @@ __device__ __forceinline__ StateRef state_of(SlotRef s) {
 template <typename T> using gptr_t = __attribute__((address_space(1))) T *;
 template <typename T> __device__ __forceinline__ gptr_t<T> gp(T *p) { return (gptr_t<T>)p; }
 
+// ---------------------------------------------------------------- XCD-aware tiling
+// The MI355X dispatches workgroups to its 8 XCDs round-robin by linear id, and
+// each XCD has its own L2.  Kernels whose tiles read halo rows of their
+// neighbours map workgroup b to tile (b % 8) * (nb / 8) + b / 8, so that every
+// XCD sweeps one contiguous band of the grid and the halo rows it re-reads are
+// in its own L2.  (Identity when nb is not a multiple of 8.)
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    return (nb % NXCD) ? b : (b % NXCD) * (nb / NXCD) + b / NXCD;
+}
+
 // ---------------------------------------------------------------- small helpers
 template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};

@@ -364,126 +364,12 @@ __global__ __launch_bounds__(NT) void k_finalize(Slot *const *slots) {
 }
 
 
-// The residual-type quantity a row-forward pass transforms, at grid point
-// (y, x), for every component: W = F(U) (FP64 kinds) or the FP32 inner residual,
-// plus the side effects of the kind (initial copies, outer-pass state) and the
-// point's contributions to the squared norm (acc[c]) and to sum(U - U^k) (acc[C + c]).
-template <typename T, int LOGN, int BC, int EQ, int KIND>
-__device__ __forceinline__ void produce_W(SlotRef s, StateRef sst, int y, int x, T *wv, double *acc) {
-    constexpr int N = 1 << LOGN;
-    constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
-    constexpr size_t NN = (size_t)N * N;
-    const int it = sst.iters;
-    const size_t g = (size_t)y * N + x;
-    if constexpr (KIND == K_INIT64 || KIND == K_ITER64) {
-        double W[C], Uc[C], ukc[C];
-        if constexpr (KIND == K_INIT64) {
-            const double *src = s.src;
-            const bool prox = s.init != 0;
-            auto acc_u = [&](int c, int dy, int dx) -> double {
-                const size_t gi = (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
-                if (!prox) return src[c * NN + gi];
-                if constexpr (EQ == EQ_LAP5) return prox_ac(src[gi], s.ht, s.b);
-                else if constexpr (EQ == EQ_SCHNAK) {
-                    double u, v;
-                    prox_schnak(src[gi], src[NN + gi], s.ht, s.sa, s.sb, s.kappa, u, v);
-                    return c == 0 ? u : v;
-                } else return src[c * NN + gi];
-            };
-#pragma unroll
-            for (int c = 0; c < C; ++c) ukc[c] = src[c * NN + g];
-            eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
-            double *U0 = (double *)s.U[0];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                U0[c * NN + g] = Uc[c];
-                s.Uk[c * NN + g] = ukc[c];
-            }
-        } else {
-            const double *Un = (const double *)s.U[(it + 1) & 1];
-            auto acc_u = [&](int c, int dy, int dx) -> double {
-                return Un[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
-            };
-#pragma unroll
-            for (int c = 0; c < C; ++c) ukc[c] = s.Uk[c * NN + g];
-            eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            acc[c] += W[c] * W[c];
-            acc[C + c] += Uc[c] - ukc[c];
-            wv[c] = (T)W[c];
-        }
-    } else if constexpr (KIND == K_INNER32) {
-        const float *E = (const float *)s.U[(it + 1) & 1];
-        const float *Ub = s.Ub32;
-        auto acc_e = [&](int c, int dy, int dx) -> float {
-            return E[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
-        };
-        auto acc_ub = [&](int c, int dy, int dx) -> float {
-            return Ub[c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N)];
-        };
-        float rc[C], W[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) rc[c] = s.r32[c * NN + g];
-        eval_Ftilde<EQ>(s, acc_e, acc_ub, rc, W);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            acc[c] += (double)W[c] * (double)W[c];
-            wv[c] = (T)W[c];
-        }
-    } else {
-        // Mixed outer pass: U_new = U + e (FP64) or the initial U; r = F(U_new) in FP64.
-        double W[C], Uc[C], ukc[C];
-        if constexpr (KIND == K_OUTER_INIT) {
-            const double *src = s.src;
-            const bool prox = s.init != 0;
-            auto acc_u = [&](int c, int dy, int dx) -> double {
-                const size_t gi = (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
-                if (!prox) return src[c * NN + gi];
-                if constexpr (EQ == EQ_LAP5) return prox_ac(src[gi], s.ht, s.b);
-                else if constexpr (EQ == EQ_SCHNAK) {
-                    double u, v;
-                    prox_schnak(src[gi], src[NN + gi], s.ht, s.sa, s.sb, s.kappa, u, v);
-                    return c == 0 ? u : v;
-                } else return src[c * NN + gi];
-            };
-#pragma unroll
-            for (int c = 0; c < C; ++c) ukc[c] = src[c * NN + g];
-            eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                s.U64[0][c * NN + g] = Uc[c];
-                s.Uk[c * NN + g] = ukc[c];
-            }
-        } else {
-            const double *Ucur = s.U64[sst.outer & 1];
-            double *Unext = s.U64[(sst.outer + 1) & 1];
-            const float *E = (const float *)s.U[sst.iters & 1];
-            const bool has_e = sst.iters > 0;
-            auto acc_u = [&](int c, int dy, int dx) -> double {
-                const size_t gi = c * NN + (size_t)wrap<BC>(y + dy, N) * N + wrap<BC>(x + dx, N);
-                return has_e ? Ucur[gi] + (double)E[gi] : Ucur[gi];
-            };
-#pragma unroll
-            for (int c = 0; c < C; ++c) ukc[c] = s.Uk[c * NN + g];
-            eval_F<EQ, double>(s, acc_u, ukc, W, Uc);
-#pragma unroll
-            for (int c = 0; c < C; ++c) Unext[c * NN + g] = Uc[c];
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            acc[c] += W[c] * W[c];
-            acc[C + c] += Uc[c] - ukc[c];
-            s.r32[c * NN + g] = (float)W[c];
-            s.Ub32[c * NN + g] = (float)Uc[c];
-            wv[c] = (T)(float)W[c];
-        }
-    }
-}
-
-// The same for the two iteration kinds, on four consecutive points (y, x0..x0+3)
-// with vector loads: wv[k][c] receives W at point k.
+// The residual-type quantity a row-forward pass transforms, on four consecutive
+// points (y, x0..x0+3) with vector loads: wv[k][c] receives, for every
+// component, W = F(U) (FP64 kinds) or the FP32 inner residual F~(e) at point k;
+// acc[c] accumulates the squared norm and acc[C + c] sum(U - U^k).  The kinds'
+// side effects: the initial kinds store U_0 and U^k, the mixed outer kinds store
+// the FP64 U, its FP32 copy and the FP32 residual r.
 template <typename T, int LOGN, int BC, int EQ, int KIND>
 __device__ __forceinline__ void produce_W4(SlotRef s, StateRef sst, int y, int x0, T (*wv)[EQ == EQ_SCHNAK ? 2 : 1],
                                            double *acc) {
@@ -493,15 +379,67 @@ __device__ __forceinline__ void produce_W4(SlotRef s, StateRef sst, int y, int x
     constexpr int HY = stencil_hy<EQ>();
     const int it = sst.iters;
     const size_t g0 = (size_t)y * N + x0;
-    if constexpr (KIND == K_ITER64) {
-        const auto Un = gp((const double *)s.U[(it + 1) & 1]);
+    if constexpr (KIND != K_INNER32) {
+        // FP64 kinds: the iterate U (window wu) and U^k at the four points
         Win<double, HY> wu[C];
         vec4_t<double> uk[C];
+        if constexpr (KIND == K_ITER64) {
+            const auto Un = gp((const double *)s.U[(it + 1) & 1]);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            load_win<double, BC, LOGN, HY>(wu[c], Un + c * NN, y, x0);
-            uk[c] = load4<double>(gp((const double *)s.Uk) + c * NN + g0);
+            for (int c = 0; c < C; ++c) {
+                load_win<double, BC, LOGN, HY>(wu[c], Un + c * NN, y, x0);
+                uk[c] = load4<double>(gp((const double *)s.Uk) + c * NN + g0);
+            }
+        } else if constexpr (KIND == K_INIT64 || KIND == K_OUTER_INIT) {
+            // U_0 = U^k, or the pointwise reaction prox of U^k (predictor)
+            const auto src = gp(s.src);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                load_win<double, BC, LOGN, HY>(wu[c], src + c * NN, y, x0);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) uk[c][k] = wu[c].at(k, 0, 0);
+            }
+            if (s.init != 0) {
+#pragma unroll
+                for (int i = 0; i < 2 * HY + 1; ++i) {
+                    const int hx = HY - (i < HY ? HY - i : i - HY);
+#pragma unroll
+                    for (int j = HY - hx; j < HY + 4 + hx; ++j) {
+                        if constexpr (EQ == EQ_LAP5) {
+                            wu[0].v[i][j] = prox_ac(wu[0].v[i][j], s.ht, s.b);
+                        } else if constexpr (EQ == EQ_SCHNAK) {
+                            double u, v;
+                            prox_schnak(wu[0].v[i][j], wu[1].v[i][j], s.ht, s.sa, s.sb, s.kappa, u, v);
+                            wu[0].v[i][j] = u;
+                            wu[1].v[i][j] = v;
+                        }
+                    }
+                }
+            }
+        } else {
+            // mixed outer update: U = U_prev + e (e absent before the first inner iteration)
+            const auto Ucur = gp((const double *)s.U64[sst.outer & 1]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                load_win<double, BC, LOGN, HY>(wu[c], Ucur + c * NN, y, x0);
+                uk[c] = load4<double>(gp((const double *)s.Uk) + c * NN + g0);
+            }
+            if (sst.iters > 0) {
+                const auto E = gp((const float *)s.U[sst.iters & 1]);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    Win<float, HY> we;
+                    load_win<float, BC, LOGN, HY>(we, E + c * NN, y, x0);
+#pragma unroll
+                    for (int i = 0; i < 2 * HY + 1; ++i) {
+                        const int hx = HY - (i < HY ? HY - i : i - HY);
+#pragma unroll
+                        for (int j = HY - hx; j < HY + 4 + hx; ++j) wu[c].v[i][j] += (double)we.v[i][j];
+                    }
+                }
+            }
         }
+        vec4_t<double> Uc4[C], W4[C];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             double W[C], Uc[C], ukc[C];
@@ -512,7 +450,33 @@ __device__ __forceinline__ void produce_W4(SlotRef s, StateRef sst, int y, int x
             for (int c = 0; c < C; ++c) {
                 acc[c] += W[c] * W[c];
                 acc[C + c] += Uc[c] - ukc[c];
-                wv[k][c] = (T)W[c];
+                Uc4[c][k] = Uc[c];
+                W4[c][k] = W[c];
+                // the mixed inner loop starts from the FP32 residual
+                wv[k][c] = (KIND == K_OUTER_INIT || KIND == K_OUTER_UPD) ? (T)(float)W[c] : (T)W[c];
+            }
+        }
+        if constexpr (KIND == K_INIT64 || KIND == K_OUTER_INIT || KIND == K_OUTER_UPD) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if constexpr (KIND == K_INIT64) {
+                    store4<double>(gp((double *)s.U[0]) + c * NN + g0, Uc4[c]);
+                } else if constexpr (KIND == K_OUTER_INIT) {
+                    store4<double>(gp(s.U64[0]) + c * NN + g0, Uc4[c]);
+                } else {
+                    store4<double>(gp(s.U64[(sst.outer + 1) & 1]) + c * NN + g0, Uc4[c]);
+                }
+                if constexpr (KIND != K_OUTER_UPD) store4<double>(gp(s.Uk) + c * NN + g0, uk[c]);
+                if constexpr (KIND != K_INIT64) {
+                    vec4_t<float> r4, ub4;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        r4[k] = (float)W4[c][k];
+                        ub4[k] = (float)Uc4[c][k];
+                    }
+                    store4<float>(gp(s.r32) + c * NN + g0, r4);
+                    store4<float>(gp(s.Ub32) + c * NN + g0, ub4);
+                }
             }
         }
     } else {
@@ -578,30 +542,17 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
 #pragma unroll
     for (int k = 0; k < 2 * C; ++k) acc[k] = 0.0;
 
-    if constexpr (KIND == K_ITER64 || KIND == K_INNER32) {
-        // four consecutive points per thread and pass, vector loads
+    // four consecutive points per thread and pass, vector loads
 #pragma unroll 2
-        for (int idx = threadIdx.x; idx < R * N / 4; idx += NT) {
-            const int r = idx >> (LOGN - 2), x0 = (idx & (N / 4 - 1)) * 4;
-            T wv[4][C];
-            produce_W4<T, LOGN, BC, EQ, KIND>(s, sst, y0 + r, x0, wv, acc);
+    for (int idx = threadIdx.x; idx < R * N / 4; idx += NT) {
+        const int r = idx >> (LOGN - 2), x0 = (idx & (N / 4 - 1)) * 4;
+        T wv[4][C];
+        produce_W4<T, LOGN, BC, EQ, KIND>(s, sst, y0 + r, x0, wv, acc);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int pos = (BC == BC_P) ? x0 + k : dct_pos(x0 + k, N);
+        for (int k = 0; k < 4; ++k) {
+            const int pos = (BC == BC_P) ? x0 + k : dct_pos(x0 + k, N);
 #pragma unroll
-                for (int c = 0; c < C; ++c) rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = wv[k][c];
-            }
-        }
-    } else {
-#pragma unroll 8
-        for (int idx = threadIdx.x; idx < R * N; idx += NT) {
-            const int r = idx >> LOGN, x = idx & (N - 1);
-            const int y = y0 + r;
-            T wv[C];
-            produce_W<T, LOGN, BC, EQ, KIND>(s, sst, y, x, wv, acc);
-            const int pos = (BC == BC_P) ? x : dct_pos(x, N);
-#pragma unroll
-            for (int c = 0; c < C; ++c) rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = wv[c];
+            for (int c = 0; c < C; ++c) rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = wv[k][c];
         }
     }
     __syncthreads();
@@ -706,22 +657,34 @@ __global__ __launch_bounds__(NT) void k_rowinv(Slot *const *slots) {
     const cplx<T> *twd = (const cplx<T> *)s.twd;
     rows_pre_inverse<T, LOGN, BC, NREG, NT>(buf, twd);
     wg_fft16<T, LOGN, +1, NREG, NT>(buf, tw);
-    T *P = (T *)s.P;
-    T *Pt = (T *)s.Pt;
+    const auto P = gp((T *)s.P);
+    const auto Pt = gp((T *)s.Pt);
     const T tp = (T)s.tau_p, om = (T)s.omega;
     const bool first = sst.iters == 0;
-#pragma unroll 8
-    for (int idx = threadIdx.x; idx < C * R * N; idx += NT) {
-        const int x = idx & (N - 1), rest = idx >> LOGN;
+    // four consecutive points per thread: vector loads and stores of P and P~
+#pragma unroll 4
+    for (int idx = threadIdx.x; idx < C * R * N / 4; idx += NT) {
+        const int x0 = (idx & (N / 4 - 1)) * 4, rest = idx >> (LOGN - 2);
         const int r = rest % R, c = rest / R;
-        const int pos = (BC == BC_P) ? x : dct_pos(x, N);
-        const cplx<T> zv = buf[rix<LOGN>(c * R / 2 + r / 2, pos)];
-        const T Y = (r & 1) ? zv.im : zv.re;
-        const size_t g = c * NN + (size_t)(y0 + r) * N + x;
-        const T Pn = first ? (T)0 : P[g];
-        const T Pn1 = Pn + tp * Y;
-        P[g] = Pn1;
-        Pt[g] = Pn1 + om * (Pn1 - Pn);
+        const size_t g = c * NN + (size_t)(y0 + r) * N + x0;
+        vec4_t<T> Pn;
+        if (first) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Pn[k] = (T)0;
+        } else {
+            Pn = load4<T>(P + g);
+        }
+        vec4_t<T> Pn1, Ptl;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int pos = (BC == BC_P) ? x0 + k : dct_pos(x0 + k, N);
+            const cplx<T> zv = buf[rix<LOGN>(c * R / 2 + r / 2, pos)];
+            const T Y = (r & 1) ? zv.im : zv.re;
+            Pn1[k] = Pn[k] + tp * Y;
+            Ptl[k] = Pn1[k] + om * (Pn1[k] - Pn[k]);
+        }
+        store4<T>(P + g, Pn1);
+        store4<T>(Pt + g, Ptl);
     }
 }
 

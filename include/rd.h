@@ -144,12 +144,13 @@ rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *c
 
 /* ---- instrumentation ------------------------------------------------------------- */
 /* Time the four kernels of one Algorithm-1 iteration on hip_stream: prepares the step
- * for u_n (DEVICE) like rd_step (stop test disabled), then for each kernel resets the
- * slot's iteration state, launches it once untimed and `reps` times back to back
- * between one pair of HIP events on that stream.  ms_out (HOST, 4 doubles) receives
- * the mean time per launch in milliseconds (kernel plus the dispatch gap between
- * dependent launches) of: column pass, inverse row pass + dual update, primal update,
- * residual + forward row pass (with its stop-decision kernel).  Synchronises.            */
+ * for u_n (DEVICE) like rd_step (stop rules disabled), runs one untimed iteration, then
+ * `reps` iterations in the solver's launch order, back to back, each launch recording
+ * a start and a stop HIP event in its own dispatch packets (the kernel's begin and end
+ * on that stream), so each kernel runs in the cache state the real loop leaves.  ms_out
+ * (HOST, 4 doubles) receives the mean duration per launch in milliseconds of: column
+ * pass (with the stop decision of the preceding row pass), inverse row pass + dual
+ * update, primal update, residual + forward row pass.  Synchronises.                   */
 rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
                                const double *u_n, int32_t reps, void *hip_stream, double *ms_out);
 

@@ -341,28 +341,50 @@ template <int KIND> __device__ __forceinline__ bool skip_launch(StateRef sst) {
 }
 
 // ---------------------------------------------------------------- stop decision
-// One workgroup per slot: reduce the row pass's per-workgroup partial sums in
-// block order (deterministic), then take the decision of finalize<KIND>.  Skips
+// Sum of the row pass's per-workgroup partials in one fixed order, whatever the
+// size of the workgroup that computes it: 64 lane sums L_l = sum_j p[l + 64 j]
+// (j increasing), then sum_l L_l (l increasing) by thread 0.  The decision is
+// taken either by k_finalize or by the extra workgroup of a column pass; both
+// give bitwise the same sums.  lanes: LDS scratch of 64 * 2C doubles.
+template <int KIND, int C, int NTHR>
+__device__ __forceinline__ void reduce_and_finalize(SlotRef s, double *lanes) {
+    constexpr int K = 2 * C;
+    const int nb = s.nblk_rows;
+    const auto part = gp((const double *)s.partials);
+    for (int l = threadIdx.x; l < 64; l += NTHR) {
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = 0.0;
+        for (int j = l; j < nb; j += 64) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] += part[j * K + k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) lanes[k * 64 + l] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double x = 0.0;
+            for (int l = 0; l < 64; ++l) x += lanes[k * 64 + l];
+            v[k] = x;
+        }
+        finalize<KIND, C>(s, v, v + C);
+    }
+}
+
+// One workgroup per slot: the stop decision of the row pass of kind KIND.  Skips
 // exactly when the row-pass launch of the same kind skipped.
 template <int KIND, int C>
 __global__ __launch_bounds__(NT) void k_finalize(Slot *const *slots) {
-    __shared__ double scratch[2 * C * (NT / 64)];
+    __shared__ double lanes[64 * 2 * C];
     SlotRef s = slot_of(slots);
-    // The partial sums are loaded before the state is tested, so that the two
-    // memory latencies overlap (reading them is harmless when the launch skips).
-    double v[2 * C];
-#pragma unroll
-    for (int k = 0; k < 2 * C; ++k) v[k] = 0.0;
-    for (int bl = threadIdx.x; bl < s.nblk_rows; bl += NT) {
-#pragma unroll
-        for (int k = 0; k < 2 * C; ++k) v[k] += s.partials[bl * (2 * C) + k];
-    }
     StateRef sst = state_of(s);
     if (skip_launch<KIND>(sst)) return;
-    block_sum<2 * C>(v, scratch);
-    if (threadIdx.x == 0) finalize<KIND, C>(s, v, v + C);
+    reduce_and_finalize<KIND, C, NT>(s, lanes);
 }
-
 
 // The residual-type quantity a row-forward pass transforms, on four consecutive
 // points (y, x0..x0+3) with vector loads: wv[k][c] receives, for every
@@ -594,15 +616,29 @@ template <typename T, int LOGN, int C> constexpr int col_jobs() {
 }
 template <typename T, int LOGN, int C> constexpr int col_threads() { return col_jobs<T, LOGN, C>() * ((1 << LOGN) / 16); }
 
-template <typename T, int LOGN, int BC, int C>
+// FIN >= 0: the launch has one extra workgroup (the last) that takes the stop
+// decision of the preceding row pass of kind FIN, in parallel with the column
+// transforms.  The other workgroups test the State as it was before that
+// decision: a slot that converges at this row pass runs one column pass more,
+// whose output nothing reads (the kernels after it see the decision).
+constexpr int FIN_NONE = -1;
+
+template <typename T, int LOGN, int BC, int C, int FIN>
 __global__ __launch_bounds__((col_threads<T, LOGN, C>())) void k_cols(Slot *const *slots) {
     constexpr int N = 1 << LOGN, H = N / 2;
     constexpr int NTH = col_threads<T, LOGN, C>();
     constexpr int CB = col_jobs<T, LOGN, C>();
     constexpr int R = rows_per_block<T, LOGN, C>();
     __shared__ cplx<T> buf[CB * lds_region<LOGN>()];
+    __shared__ double lanes[FIN == FIN_NONE ? 1 : 64 * 2 * C];
     SlotRef s = slot_of(slots);
     StateRef sst = state_of(s);
+    if constexpr (FIN != FIN_NONE) {
+        if (blockIdx.x == gridDim.x - 1) {
+            if (!skip_launch<FIN>(sst)) reduce_and_finalize<FIN, C, NTH>(s, lanes);
+            return;
+        }
+    }
     if (skip_launch<K_ITER64>(sst)) return;
     // blockIdx.x -> (component, first column); CB divides N/2
     const int c = blockIdx.x / (H / CB);

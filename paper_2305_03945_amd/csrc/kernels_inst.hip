@@ -3,6 +3,8 @@
 #include "kernels.h"
 #include "registry.h"
 
+#include <hip/hip_ext.h>
+
 #ifndef RD_LOGN
 #error "RD_LOGN must be defined by the build"
 #endif
@@ -14,36 +16,56 @@ constexpr int L = RD_LOGN;
 
 template <int EQ> constexpr int ncomp() { return EQ == EQ_SCHNAK ? 2 : 1; }
 
+inline hipEvent_t ev_start(hipEvent_t *ev) { return ev ? ev[0] : nullptr; }
+inline hipEvent_t ev_stop(hipEvent_t *ev) { return ev ? ev[1] : nullptr; }
+
 template <typename T, int EQ> constexpr int row_block() { return rows_per_block<T, L, ncomp<EQ>()>(); }
 
-// A row-forward pass is two launches: the row kernel writes per-workgroup
-// partial sums, k_finalize reduces them and takes the stop decision.
+// The row kernel writes per-workgroup partial sums; the stop decision is taken
+// by k_finalize (launch_fin) or by the extra workgroup of the next column pass.
 template <typename T, int BC, int EQ, int KIND>
-void launch_rowfwd(Slot *const *slots, int nslots, hipStream_t st) {
+void launch_rowfwd(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
     constexpr int R = row_block<T, EQ>();
-    hipLaunchKernelGGL((k_row_forward<T, L, BC, EQ, KIND>), dim3((1 << L) / R, nslots), dim3(NT), 0, st, slots);
-    hipLaunchKernelGGL((k_finalize<KIND, ncomp<EQ>()>), dim3(1, nslots), dim3(NT), 0, st, slots);
+    hipExtLaunchKernelGGL((k_row_forward<T, L, BC, EQ, KIND>), dim3((1 << L) / R, nslots), dim3(NT), 0, st,
+                          ev_start(ev), ev_stop(ev), 0, slots);
 }
 
-template <typename T, int BC, int EQ>
-void launch_cols(Slot *const *slots, int nslots, hipStream_t st) {
+template <int KIND, int EQ>
+void launch_fin(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
+    hipExtLaunchKernelGGL((k_finalize<KIND, ncomp<EQ>()>), dim3(1, nslots), dim3(NT), 0, st, ev_start(ev),
+                          ev_stop(ev), 0, slots);
+}
+
+// Initial and outer passes: row kernel, then its decision at once.
+template <typename T, int BC, int EQ, int KIND>
+void launch_rowfwd_fin(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
+    hipEvent_t e0[2] = {ev_start(ev), nullptr}, e1[2] = {nullptr, ev_stop(ev)};
+    launch_rowfwd<T, BC, EQ, KIND>(slots, nslots, st, e0);
+    launch_fin<KIND, EQ>(slots, nslots, st, e1);
+}
+
+template <typename T, int BC, int EQ, int FIN>
+void launch_cols(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
     constexpr int jobs = ncomp<EQ>() * (1 << L) / 2;
     constexpr int CB = col_jobs<T, L, ncomp<EQ>()>();
     static_assert(((1 << L) / 2) % CB == 0, "column blocks must tile a component");
-    hipLaunchKernelGGL((k_cols<T, L, BC, ncomp<EQ>()>), dim3(jobs / CB, nslots), dim3(col_threads<T, L, ncomp<EQ>()>()),
-                       0, st, slots);
+    constexpr int extra = FIN == FIN_NONE ? 0 : 1;
+    hipExtLaunchKernelGGL((k_cols<T, L, BC, ncomp<EQ>(), FIN>), dim3(jobs / CB + extra, nslots),
+                          dim3(col_threads<T, L, ncomp<EQ>()>()), 0, st, ev_start(ev), ev_stop(ev), 0, slots);
 }
 
 template <typename T, int BC, int EQ>
-void launch_rowinv(Slot *const *slots, int nslots, hipStream_t st) {
+void launch_rowinv(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
     constexpr int R = row_block<T, EQ>();
-    hipLaunchKernelGGL((k_rowinv<T, L, BC, ncomp<EQ>()>), dim3((1 << L) / R, nslots), dim3(NT), 0, st, slots);
+    hipExtLaunchKernelGGL((k_rowinv<T, L, BC, ncomp<EQ>()>), dim3((1 << L) / R, nslots), dim3(NT), 0, st,
+                          ev_start(ev), ev_stop(ev), 0, slots);
 }
 
 template <typename T, int BC, int EQ, int MODE>
-void launch_upd(Slot *const *slots, int nslots, hipStream_t st) {
+void launch_upd(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
     constexpr int blocks = ((1 << L) * (1 << L) / UPD_PPT + NT - 1) / NT;
-    hipLaunchKernelGGL((k_upd<T, L, BC, EQ, MODE>), dim3(blocks, nslots), dim3(NT), 0, st, slots);
+    hipExtLaunchKernelGGL((k_upd<T, L, BC, EQ, MODE>), dim3(blocks, nslots), dim3(NT), 0, st, ev_start(ev),
+                          ev_stop(ev), 0, slots);
 }
 
 template <typename T, int BC, int EQ>
@@ -62,19 +84,23 @@ void launch_tout(Slot *const *slots, int nslots, const double *, double *out, hi
 
 template <int BC, int EQ> void fill() {
     KSet &f = g_kernels[MODE_F64][L][BC][EQ];
-    f.init = launch_rowfwd<double, BC, EQ, K_INIT64>;
+    f.init = launch_rowfwd_fin<double, BC, EQ, K_INIT64>;
     f.rowfwd = launch_rowfwd<double, BC, EQ, K_ITER64>;
-    f.cols = launch_cols<double, BC, EQ>;
+    f.fin = launch_fin<K_ITER64, EQ>;
+    f.cols = launch_cols<double, BC, EQ, FIN_NONE>;
+    f.cols_fin = launch_cols<double, BC, EQ, K_ITER64>;
     f.rowinv = launch_rowinv<double, BC, EQ>;
     f.upd = launch_upd<double, BC, EQ, MODE_F64>;
     f.tin = launch_tin<double, BC, EQ>;
     f.tout = launch_tout<double, BC, EQ>;
     f.rows_per_block = row_block<double, EQ>();
     KSet &m = g_kernels[MODE_MIXED][L][BC][EQ];
-    m.init = launch_rowfwd<float, BC, EQ, K_OUTER_INIT>;
-    m.outer = launch_rowfwd<float, BC, EQ, K_OUTER_UPD>;
+    m.init = launch_rowfwd_fin<float, BC, EQ, K_OUTER_INIT>;
+    m.outer = launch_rowfwd_fin<float, BC, EQ, K_OUTER_UPD>;
     m.rowfwd = launch_rowfwd<float, BC, EQ, K_INNER32>;
-    m.cols = launch_cols<float, BC, EQ>;
+    m.fin = launch_fin<K_INNER32, EQ>;
+    m.cols = launch_cols<float, BC, EQ, FIN_NONE>;
+    m.cols_fin = launch_cols<float, BC, EQ, K_INNER32>;
     m.rowinv = launch_rowinv<float, BC, EQ>;
     m.upd = launch_upd<float, BC, EQ, MODE_MIXED>;
     m.tin = launch_tin<float, BC, EQ>;

@@ -7,15 +7,19 @@
 
 namespace rdk {
 
-typedef void (*launch_fn)(Slot *const *slots, int nslots, hipStream_t st);
+// ev: nullptr, or {start, stop} events that the dispatch packets of the launch
+// record (start of its first kernel, end of its last), for kernel timing.
+typedef void (*launch_fn)(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev);
 typedef void (*launch_io_fn)(Slot *const *slots, int nslots, const double *in, double *out, hipStream_t st);
 
 struct KSet {
     launch_fn init = nullptr;       // FP64: K_INIT64; mixed: K_OUTER_INIT
     launch_fn cols = nullptr;       // column pass (T)
+    launch_fn cols_fin = nullptr;   // column pass + stop decision of the preceding iteration row pass
+    launch_fn fin = nullptr;        // stop decision of an iteration row pass (k_finalize)
     launch_fn rowinv = nullptr;     // inverse rows + dual update (T)
     launch_fn upd = nullptr;        // primal update (T)
-    launch_fn rowfwd = nullptr;     // FP64: K_ITER64; mixed: K_INNER32
+    launch_fn rowfwd = nullptr;     // FP64: K_ITER64; mixed: K_INNER32 (no decision)
     launch_fn outer = nullptr;      // mixed: K_OUTER_UPD
     launch_io_fn tin = nullptr;     // precond-only: FP64 W -> row transforms into S
     launch_io_fn tout = nullptr;    // precond-only: S -> inverse rows -> FP64 Y

@@ -368,24 +368,22 @@ void bind_workspace(Slot &s, const Workspace &w, const Tables &t) {
 // `slots`: device array of nslots Slot pointers.  Each call enqueues `iters`
 // PDHG iterations (FP64), or `passes` rounds of `iters` inner iterations each
 // followed by an outer FP64 pass (mixed).  Finished slots turn them into no-ops.
+// One chunk of iterations.  Every chunk starts after a decided row pass (the
+// initial or outer pass with its k_finalize, or the previous chunk's final
+// k_finalize); inside it, each column pass takes the decision of the row pass
+// before it, and the chunk (or the inner loop before an outer pass) ends with a
+// k_finalize so that the host and the outer pass see a decided State.
 void enqueue_round(const KSet &k, int mode, Slot *const *slots, int nslots, int iters, int passes, hipStream_t st) {
-    if (mode == MODE_F64) {
+    const int np = mode == MODE_F64 ? 1 : passes;
+    for (int p = 0; p < np; ++p) {
         for (int i = 0; i < iters; ++i) {
-            k.cols(slots, nslots, st);
-            k.rowinv(slots, nslots, st);
-            k.upd(slots, nslots, st);
-            k.rowfwd(slots, nslots, st);
+            (i == 0 ? k.cols : k.cols_fin)(slots, nslots, st, nullptr);
+            k.rowinv(slots, nslots, st, nullptr);
+            k.upd(slots, nslots, st, nullptr);
+            k.rowfwd(slots, nslots, st, nullptr);
         }
-    } else {
-        for (int p = 0; p < passes; ++p) {
-            for (int i = 0; i < iters; ++i) {
-                k.cols(slots, nslots, st);
-                k.rowinv(slots, nslots, st);
-                k.upd(slots, nslots, st);
-                k.rowfwd(slots, nslots, st);
-            }
-            k.outer(slots, nslots, st);
-        }
+        k.fin(slots, nslots, st, nullptr);
+        if (mode == MODE_MIXED) k.outer(slots, nslots, st, nullptr);
     }
 }
 
@@ -425,7 +423,7 @@ rd_status get_step_workspace(Ctx *c, const Desc &d, int mode, Workspace *&out) {
 // Run one step to completion on the workspace's single slot.
 rd_status run_step(Ctx *c, Workspace &w, const KSet &k, hipStream_t st, int max_iter, int max_outer) {
     Slot *const *slots = w.slot_list_dev;
-    k.init(slots, 1, st);
+    k.init(slots, 1, st, nullptr);
     RD_CHECK(hipGetLastError());
     int issued = 0, rounds = 0;
     while (true) {
@@ -606,35 +604,45 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
     s.max_iter = 1 << 30;   // the stop decision must not end the timed launches
     s.tol = 0.0;
     RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
-    k.init(w->slot_list_dev, 1, st);
+    k.init(w->slot_list_dev, 1, st, nullptr);
+    // One untimed iteration from the initial state, its row pass left undecided.
+    k.cols(w->slot_list_dev, 1, st, nullptr);
+    k.rowinv(w->slot_list_dev, 1, st, nullptr);
+    k.upd(w->slot_list_dev, 1, st, nullptr);
+    k.rowfwd(w->slot_list_dev, 1, st, nullptr);
     RD_CHECK(hipGetLastError());
     RD_CHECK(hipStreamSynchronize(st));
-    // State that every kernel treats as "iteration 1 of a running step".
+    // No stop rule may end the timed iterations: tolerance 0 and max_iter 2^30 are
+    // in the slot; the mixed inner loop's target and stall rule are disabled here.
     State run{};
     RD_CHECK(hipMemcpy(&run, w->proto.st, sizeof(State), hipMemcpyDeviceToHost));
+    if (run.status != ST_OK) return RD_E_NONFINITE;
     run.done = 0;
     run.outer_done = 0;
-    run.iters = 1;
+    run.inner_target = 0.0;
+    run.inner_best = 0.0;
+    run.inner_best_it = 1 << 29;
     if (run.res0 == 0.0) run.res0 = 1.0;
     *w->st_host = run;
-    // Both iterate buffers hold the same valid field, so that the alternating
-    // buffer of back-to-back launches never reads uninitialised memory.
-    const size_t te = mode == MODE_F64 ? 8 : 4;
-    RD_CHECK(hipMemcpyAsync(w->proto.U[1], w->proto.U[0], field_bytes(d.N, d.C, te), hipMemcpyDeviceToDevice, st));
-    launch_fn fns[4] = {k.cols, k.rowinv, k.upd, k.rowfwd};
-    std::vector<hipEvent_t> ev(2);
+    RD_CHECK(hipMemcpyAsync(w->proto.st, w->st_host, sizeof(State), hipMemcpyHostToDevice, st));
+    // reps iterations in the solver's launch order, back to back; every launch's
+    // dispatch packets record a start and a stop event (the kernel's own begin and
+    // end), so each kernel is timed in the cache state the real loop leaves it.
+    launch_fn fns[4] = {k.cols_fin, k.rowinv, k.upd, k.rowfwd};
+    std::vector<hipEvent_t> ev(8 * (size_t)reps);
     for (auto &e : ev) RD_CHECK(hipEventCreate(&e));
+    for (int i = 0; i < reps; ++i)
+        for (int kk = 0; kk < 4; ++kk) fns[kk](w->slot_list_dev, 1, st, &ev[8 * i + 2 * kk]);
+    RD_CHECK(hipGetLastError());
+    RD_CHECK(hipStreamSynchronize(st));
     for (int kk = 0; kk < 4; ++kk) {
-        RD_CHECK(hipMemcpyAsync(w->proto.st, w->st_host, sizeof(State), hipMemcpyHostToDevice, st));
-        fns[kk](w->slot_list_dev, 1, st);  // untimed first launch
-        RD_CHECK(hipEventRecord(ev[0], st));
-        for (int i = 0; i < reps; ++i) fns[kk](w->slot_list_dev, 1, st);
-        RD_CHECK(hipEventRecord(ev[1], st));
-        RD_CHECK(hipGetLastError());
-        RD_CHECK(hipStreamSynchronize(st));
-        float ms = 0.f;
-        RD_CHECK(hipEventElapsedTime(&ms, ev[0], ev[1]));
-        ms_out[kk] = (double)ms / reps;
+        double tot = 0.0;
+        for (int i = 0; i < reps; ++i) {
+            float ms = 0.f;
+            RD_CHECK(hipEventElapsedTime(&ms, ev[8 * i + 2 * kk], ev[8 * i + 2 * kk + 1]));
+            tot += ms;
+        }
+        ms_out[kk] = tot / reps;
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     return RD_OK;
@@ -706,7 +714,7 @@ rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_
     RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
     RD_CHECK(hipMemsetAsync(w->proto.st, 0, sizeof(State), st));   // done = 0: column pass active
     k.tin(w->slot_list_dev, 1, w_in, nullptr, st);
-    k.cols(w->slot_list_dev, 1, st);
+    k.cols(w->slot_list_dev, 1, st, nullptr);
     k.tout(w->slot_list_dev, 1, nullptr, y, st);
     RD_CHECK(hipGetLastError());
     RD_CHECK(hipStreamSynchronize(st));
@@ -905,7 +913,7 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
             }
             Slot **dev = nullptr;
             if ((r = batch_list(c, key, 0, si->second, dev, st)) != RD_OK) return r;
-            k.init(dev, (int)si->second.size(), st);
+            k.init(dev, (int)si->second.size(), st, nullptr);
             RD_CHECK(hipGetLastError());
         }
         Slot **dev = nullptr;

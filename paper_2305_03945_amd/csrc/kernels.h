@@ -545,6 +545,37 @@ __device__ __forceinline__ size_t spec_off(int c, int y, int kx, int N) {
     return (size_t)c * H * N + ((size_t)(y / R) * H + kx) * R + (y % R);
 }
 
+// Spectrum entries are moved SV at a time, 16 bytes per access: two FP32
+// complex values (rows r, r + 1 of a tile, adjacent in S) or one FP64 value.
+template <typename T> constexpr int spec_vec() { return sizeof(T) == 4 ? 2 : 1; }
+template <typename T> __device__ __forceinline__ void spec_load(const cplx<T> *p, cplx<T> *out) {
+    if constexpr (sizeof(T) == 4) {
+        const vec4_t<float> v = load4<float>(gp((const float *)p));
+        out[0] = {v[0], v[1]};
+        out[1] = {v[2], v[3]};
+    } else {
+        typedef double v2d __attribute__((ext_vector_type(2)));
+        const v2d v = *(const gptr_t<const v2d>)gp((const double *)p);
+        out[0] = {v[0], v[1]};
+    }
+}
+template <typename T> __device__ __forceinline__ void spec_store(cplx<T> *p, const cplx<T> *in) {
+    if constexpr (sizeof(T) == 4) {
+        vec4_t<float> v;
+        v[0] = in[0].re;
+        v[1] = in[0].im;
+        v[2] = in[1].re;
+        v[3] = in[1].im;
+        store4<float>(gp((float *)p), v);
+    } else {
+        typedef double v2d __attribute__((ext_vector_type(2)));
+        v2d v;
+        v[0] = in[0].re;
+        v[1] = in[0].im;
+        *(gptr_t<v2d>)gp((double *)p) = v;
+    }
+}
+
 // ---------------------------------------------------------------- row pass, forward
 template <typename T, int LOGN, int BC, int EQ, int KIND>
 __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
@@ -582,13 +613,27 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
     const cplx<T> *twd = (const cplx<T> *)s.twd;
     wg_fft16<T, LOGN, -1, NREG, NT>(buf, tw);
     rows_post_forward<T, LOGN, BC, NREG, NT>(buf, twd);
-    // Tile store: this workgroup's R rows are one contiguous block per component.
+    // Tile store: this workgroup's R rows are one contiguous block per component;
+    // every access of the block is issued before any completes.
     cplx<T> *S = (cplx<T> *)s.S;
-#pragma unroll 8
-    for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
-        const int r = idx % R, rest = idx / R;
-        const int kx = rest % H, c = rest / H;
-        S[spec_off<R>(c, y0 + r, kx, N)] = buf[rix<LOGN>(c * R / 2 + r / 2, (r & 1) * H + kx)];
+    {
+        constexpr int SV = spec_vec<T>();
+        constexpr int TOT = C * R * H / SV;
+#pragma unroll
+        for (int i = 0; i < (TOT + NT - 1) / NT; ++i) {
+            const int idx = threadIdx.x + i * NT;
+            if (TOT % NT == 0 || idx < TOT) {
+                const int r0 = (idx % (R / SV)) * SV, rest = idx / (R / SV);
+                const int kx = rest % H, c = rest / H;
+                cplx<T> v[SV];
+#pragma unroll
+                for (int q = 0; q < SV; ++q) {
+                    const int r = r0 + q;
+                    v[q] = buf[rix<LOGN>(c * R / 2 + r / 2, (r & 1) * H + kx)];
+                }
+                spec_store<T>(&S[spec_off<R>(c, y0 + r0, kx, N)], v);
+            }
+        }
     }
     write_partials<C>(s, tile, acc, scratch);
 }
@@ -644,14 +689,25 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>())) void k_cols(Slot *cons
     const int c = blockIdx.x / (H / CB);
     const int kx0 = (blockIdx.x % (H / CB)) * CB;
     cplx<T> *S = (cplx<T> *)s.S;
-    // consecutive threads: rows of a tile, then columns, then tiles
-#pragma unroll 8
-    for (int idx = threadIdx.x; idx < CB * N; idx += NTH) {
-        const int r = idx % R, rest = idx / R;
-        const int reg = rest % CB, yt = rest / CB;
-        const int y = yt * R + r;
-        const int pos = (BC == BC_P) ? y : dct_pos(y, N);
-        buf[rix<LOGN>(reg, pos)] = S[spec_off<R>(c, y, kx0 + reg, N)];
+    // consecutive threads: rows of a tile, then columns, then tiles; every load of
+    // the block is issued before any completes
+    constexpr int SV = spec_vec<T>();
+    constexpr int TOT = CB * N / SV;
+#pragma unroll
+    for (int i = 0; i < (TOT + NTH - 1) / NTH; ++i) {
+        const int idx = threadIdx.x + i * NTH;
+        if (TOT % NTH == 0 || idx < TOT) {
+            const int r0 = (idx % (R / SV)) * SV, rest = idx / (R / SV);
+            const int reg = rest % CB, yt = rest / CB;
+            const int y = yt * R + r0;
+            cplx<T> v[SV];
+            spec_load<T>(&S[spec_off<R>(c, y, kx0 + reg, N)], v);
+#pragma unroll
+            for (int q = 0; q < SV; ++q) {
+                const int pos = (BC == BC_P) ? y + q : dct_pos(y + q, N);
+                buf[rix<LOGN>(reg, pos)] = v[q];
+            }
+        }
     }
     __syncthreads();
     const cplx<T> *tw = (const cplx<T> *)s.tw;
@@ -659,13 +715,21 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>())) void k_cols(Slot *cons
     wg_fft16<T, LOGN, -1, CB, NTH>(buf, tw);
     cols_apply_symbol<T, LOGN, BC, CB, NTH>(buf, c * H + kx0, CB, s, twd);
     wg_fft16<T, LOGN, +1, CB, NTH>(buf, tw);
-#pragma unroll 8
-    for (int idx = threadIdx.x; idx < CB * N; idx += NTH) {
-        const int r = idx % R, rest = idx / R;
-        const int reg = rest % CB, yt = rest / CB;
-        const int y = yt * R + r;
-        const int pos = (BC == BC_P) ? y : dct_pos(y, N);
-        S[spec_off<R>(c, y, kx0 + reg, N)] = buf[rix<LOGN>(reg, pos)];
+#pragma unroll
+    for (int i = 0; i < (TOT + NTH - 1) / NTH; ++i) {
+        const int idx = threadIdx.x + i * NTH;
+        if (TOT % NTH == 0 || idx < TOT) {
+            const int r0 = (idx % (R / SV)) * SV, rest = idx / (R / SV);
+            const int reg = rest % CB, yt = rest / CB;
+            const int y = yt * R + r0;
+            cplx<T> v[SV];
+#pragma unroll
+            for (int q = 0; q < SV; ++q) {
+                const int pos = (BC == BC_P) ? y + q : dct_pos(y + q, N);
+                v[q] = buf[rix<LOGN>(reg, pos)];
+            }
+            spec_store<T>(&S[spec_off<R>(c, y, kx0 + reg, N)], v);
+        }
     }
 }
 
@@ -682,11 +746,24 @@ __global__ __launch_bounds__(NT) void k_rowinv(Slot *const *slots) {
     const int y0 = blockIdx.x * R;
     const size_t NN = (size_t)N * N;
     const cplx<T> *S = (const cplx<T> *)s.S;
-#pragma unroll 8
-    for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
-        const int r = idx % R, rest = idx / R;
-        const int kx = rest % H, c = rest / H;
-        buf[rix<LOGN>(c * R / 2 + r / 2, (r & 1) * H + kx)] = S[spec_off<R>(c, y0 + r, kx, N)];
+    {
+        constexpr int SV = spec_vec<T>();
+        constexpr int TOT = C * R * H / SV;
+#pragma unroll
+        for (int i = 0; i < (TOT + NT - 1) / NT; ++i) {
+            const int idx = threadIdx.x + i * NT;
+            if (TOT % NT == 0 || idx < TOT) {
+                const int r0 = (idx % (R / SV)) * SV, rest = idx / (R / SV);
+                const int kx = rest % H, c = rest / H;
+                cplx<T> v[SV];
+                spec_load<T>(&S[spec_off<R>(c, y0 + r0, kx, N)], v);
+#pragma unroll
+                for (int q = 0; q < SV; ++q) {
+                    const int r = r0 + q;
+                    buf[rix<LOGN>(c * R / 2 + r / 2, (r & 1) * H + kx)] = v[q];
+                }
+            }
+        }
     }
     __syncthreads();
     const cplx<T> *tw = (const cplx<T> *)s.tw;

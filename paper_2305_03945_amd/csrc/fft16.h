@@ -60,16 +60,53 @@ template <typename T, int R, int DIR> __device__ __forceinline__ void dftR(cplx<
     else dft2<T, DIR>(v);
 }
 
+// Radix and butterfly count of pass q of a length-2^LOGN transform: radix 16
+// while at least 4 bits remain, then one pass of radix 8, 4 or 2.
+template <int LOGN> constexpr int npasses16() { return (LOGN + 3) / 4; }
+template <int LOGN> constexpr int pass_radix(int q) { return LOGN - 4 * q >= 4 ? 16 : (1 << (LOGN - 4 * q)); }
+
+// The twiddles of one thread for every pass after the first: for butterfly b of
+// pass q, the gathered powers W^{k}, W^{2k}, W^{4k}, W^{8k} (forward sign) of
+// W = exp(-2 pi i / (NS R)), k = j mod NS.  They depend only on the thread's
+// index in its transform team, so a kernel loads them once, at its start, and
+// every transform (forward and inverse) of the kernel reuses them.
+template <typename T, int LOGN> struct Tw16 {
+    cplx<T> p[npasses16<LOGN>() > 1 ? npasses16<LOGN>() - 1 : 1][8][4];
+};
+
+template <typename T, int LOGN>
+__device__ __forceinline__ void load_tw16(Tw16<T, LOGN> &w, const cplx<T> *__restrict__ tw) {
+    constexpr int N = 1 << LOGN;
+    constexpr int TPF = N / 16;
+    const int t = threadIdx.x % TPF;
+    const auto tg = gp(tw);
+#pragma unroll
+    for (int q = 1; q < npasses16<LOGN>(); ++q) {
+        const int R = pass_radix<LOGN>(q), NS = 1 << (4 * q);
+        const int TWSTEP = N / (NS * R);
+#pragma unroll
+        for (int b = 0; b < 16 / R; ++b) {
+            const int k = (t + b * TPF) & (NS - 1);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if ((1 << e) < R) {
+                    const int i = ((k * TWSTEP) << e) & (N - 1);
+                    w.p[q - 1][b][e] = {tg[i].re, tg[i].im};
+                }
+        }
+    }
+}
+
 // One Stockham pass of radix R (NS = product of earlier radices).  Butterfly j
 // reads x[j + r N/R], twiddles input r by W_{NS R}^{r k} (k = j mod NS), applies
-// DFT_R, and writes output q to ((j - k) R + k) + q NS.
+// DFT_R, and writes output q to ((j - k) R + k) + q NS.  pw: the thread's
+// gathered powers for this pass (unused when NS = 1).
 template <typename T, int LOGN, int R, int NS, int DIR>
-__device__ __forceinline__ void pass16(cplx<T> *x, int t, bool active, const cplx<T> *__restrict__ tw) {
+__device__ __forceinline__ void pass16(cplx<T> *x, int t, bool active, const cplx<T> (*pw)[4]) {
     constexpr int N = 1 << LOGN;
     constexpr int TPF = N / 16;      // threads per transform
     constexpr int NB = N / R;        // butterflies
     constexpr int BPT = 16 / R;      // butterflies per thread
-    constexpr int TWSTEP = N / (NS * R);
     cplx<T> v[BPT][R];
     if (active) {
 #pragma unroll
@@ -78,12 +115,11 @@ __device__ __forceinline__ void pass16(cplx<T> *x, int t, bool active, const cpl
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b][r] = x[lds_pad(j + r * NB)];
             if constexpr (NS > 1) {
-                const int k = j & (NS - 1);
                 cplx<T> p[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     if ((1 << e) < R) {
-                        p[e] = tw[((k * TWSTEP) << e) & (N - 1)];
+                        p[e] = pw[b][e];
                         if constexpr (DIR > 0) p[e].im = -p[e].im;
                     }
 #pragma unroll
@@ -117,21 +153,23 @@ __device__ __forceinline__ void pass16(cplx<T> *x, int t, bool active, const cpl
 }
 
 template <typename T, int LOGN, int DIR, int DONE>
-__device__ __forceinline__ void passes16(cplx<T> *x, int t, bool active, const cplx<T> *tw) {
+__device__ __forceinline__ void passes16(cplx<T> *x, int t, bool active, const Tw16<T, LOGN> &w) {
     if constexpr (DONE < LOGN) {
         constexpr int REM = LOGN - DONE;
         constexpr int R = REM >= 4 ? 16 : (1 << REM);
         constexpr int LOGR = REM >= 4 ? 4 : REM;
-        pass16<T, LOGN, R, (1 << DONE), DIR>(x, t, active, tw);
-        passes16<T, LOGN, DIR, DONE + LOGR>(x, t, active, tw);
+        constexpr int q = DONE / 4;
+        pass16<T, LOGN, R, (1 << DONE), DIR>(x, t, active, w.p[q > 0 ? q - 1 : 0]);
+        passes16<T, LOGN, DIR, DONE + LOGR>(x, t, active, w);
     }
 }
 
 // In-place transforms of NREG regions (region i at buf + i * lds_region<LOGN>(),
 // padded indexing) by a workgroup of NTH threads; teams of N/16 threads take
 // regions round-robin.  Ends with a barrier.  DIR -1 forward, +1 inverse.
+// w: the thread's twiddles (load_tw16).
 template <typename T, int LOGN, int DIR, int NREG, int NTH>
-__device__ __forceinline__ void wg_fft16(cplx<T> *buf, const cplx<T> *__restrict__ tw) {
+__device__ __forceinline__ void wg_fft16(cplx<T> *buf, const Tw16<T, LOGN> &w) {
     constexpr int TPF = (1 << LOGN) / 16;
     static_assert(NTH % TPF == 0 || TPF > NTH, "team must divide the workgroup");
     constexpr int NTEAMS = NTH / TPF;
@@ -140,7 +178,7 @@ __device__ __forceinline__ void wg_fft16(cplx<T> *buf, const cplx<T> *__restrict
     for (int g = 0; g < NREG; g += NTEAMS) {
         const int reg = g + team;
         const bool active = reg < NREG;
-        passes16<T, LOGN, DIR, 0>(buf + (active ? reg : 0) * lds_region<LOGN>(), t, active, tw);
+        passes16<T, LOGN, DIR, 0>(buf + (active ? reg : 0) * lds_region<LOGN>(), t, active, w);
     }
 }
 

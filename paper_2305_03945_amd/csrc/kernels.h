@@ -591,6 +591,8 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int y0 = tile * R;
+    Tw16<T, LOGN> twr;
+    load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
     double acc[2 * C];
 #pragma unroll
     for (int k = 0; k < 2 * C; ++k) acc[k] = 0.0;
@@ -609,9 +611,8 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
         }
     }
     __syncthreads();
-    const cplx<T> *tw = (const cplx<T> *)s.tw;
     const cplx<T> *twd = (const cplx<T> *)s.twd;
-    wg_fft16<T, LOGN, -1, NREG, NT>(buf, tw);
+    wg_fft16<T, LOGN, -1, NREG, NT>(buf, twr);
     rows_post_forward<T, LOGN, BC, NREG, NT>(buf, twd);
     // Tile store: this workgroup's R rows are one contiguous block per component;
     // every access of the block is issued before any completes.
@@ -688,6 +689,8 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>())) void k_cols(Slot *cons
     // blockIdx.x -> (component, first column); CB divides N/2
     const int c = blockIdx.x / (H / CB);
     const int kx0 = (blockIdx.x % (H / CB)) * CB;
+    Tw16<T, LOGN> twr;
+    load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
     cplx<T> *S = (cplx<T> *)s.S;
     // consecutive threads: rows of a tile, then columns, then tiles; every load of
     // the block is issued before any completes
@@ -710,11 +713,10 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>())) void k_cols(Slot *cons
         }
     }
     __syncthreads();
-    const cplx<T> *tw = (const cplx<T> *)s.tw;
     const cplx<T> *twd = (const cplx<T> *)s.twd;
-    wg_fft16<T, LOGN, -1, CB, NTH>(buf, tw);
+    wg_fft16<T, LOGN, -1, CB, NTH>(buf, twr);
     cols_apply_symbol<T, LOGN, BC, CB, NTH>(buf, c * H + kx0, CB, s, twd);
-    wg_fft16<T, LOGN, +1, CB, NTH>(buf, tw);
+    wg_fft16<T, LOGN, +1, CB, NTH>(buf, twr);
 #pragma unroll
     for (int i = 0; i < (TOT + NTH - 1) / NTH; ++i) {
         const int idx = threadIdx.x + i * NTH;
@@ -745,6 +747,8 @@ __global__ __launch_bounds__(NT) void k_rowinv(Slot *const *slots) {
     if (skip_launch<K_ITER64>(sst)) return;
     const int y0 = blockIdx.x * R;
     const size_t NN = (size_t)N * N;
+    Tw16<T, LOGN> twr;
+    load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
     const cplx<T> *S = (const cplx<T> *)s.S;
     {
         constexpr int SV = spec_vec<T>();
@@ -766,10 +770,9 @@ __global__ __launch_bounds__(NT) void k_rowinv(Slot *const *slots) {
         }
     }
     __syncthreads();
-    const cplx<T> *tw = (const cplx<T> *)s.tw;
     const cplx<T> *twd = (const cplx<T> *)s.twd;
     rows_pre_inverse<T, LOGN, BC, NREG, NT>(buf, twd);
-    wg_fft16<T, LOGN, +1, NREG, NT>(buf, tw);
+    wg_fft16<T, LOGN, +1, NREG, NT>(buf, twr);
     const auto P = gp((T *)s.P);
     const auto Pt = gp((T *)s.Pt);
     const T tp = (T)s.tau_p, om = (T)s.omega;
@@ -932,7 +935,11 @@ __global__ __launch_bounds__(NT) void k_rows_transform_in(Slot *const *slots, co
         rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = (T)W[c * NN + (size_t)(y0 + r) * N + x];
     }
     __syncthreads();
-    wg_fft16<T, LOGN, -1, NREG, NT>(buf, (const cplx<T> *)s.tw);
+    {
+        Tw16<T, LOGN> twr;
+        load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
+        wg_fft16<T, LOGN, -1, NREG, NT>(buf, twr);
+    }
     rows_post_forward<T, LOGN, BC, NREG, NT>(buf, (const cplx<T> *)s.twd);
     cplx<T> *S = (cplx<T> *)s.S;
 #pragma unroll 8
@@ -952,6 +959,8 @@ __global__ __launch_bounds__(NT) void k_rows_transform_out(Slot *const *slots, d
     SlotRef s = slot_of(slots);
     const int y0 = blockIdx.x * R;
     const size_t NN = (size_t)N * N;
+    Tw16<T, LOGN> twr;
+    load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
     const cplx<T> *S = (const cplx<T> *)s.S;
 #pragma unroll 8
     for (int idx = threadIdx.x; idx < C * R * H; idx += NT) {
@@ -961,7 +970,7 @@ __global__ __launch_bounds__(NT) void k_rows_transform_out(Slot *const *slots, d
     }
     __syncthreads();
     rows_pre_inverse<T, LOGN, BC, NREG, NT>(buf, (const cplx<T> *)s.twd);
-    wg_fft16<T, LOGN, +1, NREG, NT>(buf, (const cplx<T> *)s.tw);
+    wg_fft16<T, LOGN, +1, NREG, NT>(buf, twr);
 #pragma unroll 8
     for (int idx = threadIdx.x; idx < C * R * N; idx += NT) {
         const int x = idx & (N - 1), rest = idx >> LOGN;

@@ -126,6 +126,52 @@ size_t rd_footprint_bytes(const rd_problem *prob, const rd_opts *opts);
 rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
                   const double *u_n, double *u_np1, void *hip_stream, rd_info *info);
 
+/* ---- adaptive time step size (Sec. 2.2, "Adaptive time stepsize") ---------------------- */
+/* Rule: after a step of size h that took M PDHG iterations (rd_info.iters; mixed: inner
+ * iterations), the next step uses eta h if M > n_hi (N^*), h / eta if M < n_lo (N_*) and
+ * h / eta <= ht0 (h_t^0), else h.  A step whose solve failed (RD_E_NOCONV or
+ * RD_E_NONFINITE) is rejected and retried with eta h (the paper is silent on failed
+ * steps; this is the reading taken).                                                     */
+typedef struct {
+    double ht0;              /* first and largest step size h_t^0 (> 0)                   */
+    double eta;              /* rescaling coefficient, 0 < eta < 1                        */
+    int32_t n_hi;            /* N^*: shrink above this many iterations                    */
+    int32_t n_lo;            /* N_*: enlarge below this many (0 < n_lo < n_hi)            */
+    double ht_min;           /* a rejected step whose retry would go below this ends the
+                                run with RD_E_NOCONV (>= 0)                                 */
+    int32_t max_rejects;     /* consecutive rejections allowed before RD_E_NOCONV (>= 0)  */
+    int32_t pad0;
+} rd_adapt;
+
+typedef struct {
+    int32_t accepted;        /* steps taken                                               */
+    int32_t rejected;        /* failed solves retried with a smaller step                 */
+    int32_t shrinks;         /* decisions that reduced the step size (rejections included) */
+    int32_t enlarges;        /* decisions that increased it                               */
+    int64_t pdhg_iters;      /* PDHG iterations of all solves, rejected ones included     */
+    double t;                /* time reached                                              */
+    double ht;               /* step size the next step would use                         */
+    int32_t status;          /* RD_OK, or RD_E_NOCONV when the rejections ran out          */
+    int32_t pad0;
+} rd_adapt_info;
+
+/* The rule alone, host logic only: step size h used, the step's iteration count and
+ * status -> *ht_next (HOST) and *accept (HOST, 1 or 0).  RD_E_INVALID for a bad rd_adapt. */
+rd_status rd_adapt_next(const rd_adapt *adapt, double h, int32_t iters, int32_t step_status,
+                        double *ht_next, int32_t *accept);
+
+/* Advance u (DEVICE, [c][N][N] FP64, read and overwritten) from t0 to t_end with rd_step
+ * solves and the rule above, starting at h = min(ht0, t_end - t0); every step is shortened
+ * to land on t_end (h = min(h_t, t_end - t)); the run ends when t_end - t <=
+ * 1e-14 max(1, |t_end|).  Rejected steps leave u unchanged.  info (HOST) receives the
+ * counters; if trace_cap > 0, trace_h / trace_iters / trace_ok (HOST, trace_cap entries
+ * each) receive the size, iteration count and acceptance of the first trace_cap solves.
+ * Allocates one field-sized device buffer for the call.  Returns info->status, or an
+ * argument / device error.  Synchronises.                                                */
+rd_status rd_advance(void *ctx, const rd_problem *prob, const rd_opts *opts, const rd_adapt *adapt,
+                     double t0, double t_end, double *u, void *hip_stream, rd_adapt_info *info,
+                     double *trace_h, int32_t *trace_iters, int32_t *trace_ok, int32_t trace_cap);
+
 /* ---- kernel-level entry points (the pieces of one iteration) ------------------------ */
 /* W = F(U) (Sec. 2.1 eq. 12; Sec. 3.2 eq. 29; Sec. 3.4.1).  u, uk, w: DEVICE, [c][N][N].
  * *res_l2 (HOST) receives ||W / h_t||_2 summed over components.  Synchronises.          */

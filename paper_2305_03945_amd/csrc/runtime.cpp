@@ -648,6 +648,106 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
     return RD_OK;
 }
 
+// ---------------------------------------------------------------- adaptive time step size
+}  // extern "C"
+
+namespace {
+bool check_adapt(const rd_adapt *a) {
+    return a && a->ht0 > 0.0 && std::isfinite(a->ht0) && a->eta > 0.0 && a->eta < 1.0 && a->n_lo > 0 &&
+           a->n_hi > a->n_lo && a->ht_min >= 0.0 && a->max_rejects >= 0;
+}
+bool reached(double t, double t_end) { return t_end - t <= 1e-14 * std::max(1.0, std::fabs(t_end)); }
+}  // namespace
+
+extern "C" {
+
+rd_status rd_adapt_next(const rd_adapt *a, double h, int32_t iters, int32_t step_status, double *ht_next,
+                        int32_t *accept) {
+    if (!check_adapt(a) || !ht_next || !accept || !(h > 0.0)) return RD_E_INVALID;
+    if (step_status != RD_OK) {
+        *ht_next = a->eta * h;
+        *accept = 0;
+        return RD_OK;
+    }
+    *accept = 1;
+    if (iters > a->n_hi) {
+        *ht_next = a->eta * h;
+    } else if (iters < a->n_lo) {
+        const double up = h / a->eta;
+        *ht_next = up <= a->ht0 ? up : h;
+    } else {
+        *ht_next = h;
+    }
+    return RD_OK;
+}
+
+rd_status rd_advance(void *ctx, const rd_problem *prob, const rd_opts *opts, const rd_adapt *a, double t0,
+                     double t_end, double *u, void *hip_stream, rd_adapt_info *info, double *trace_h,
+                     int32_t *trace_iters, int32_t *trace_ok, int32_t trace_cap) {
+    if (!ctx || !u || !info || !check_adapt(a) || !std::isfinite(t0) || !std::isfinite(t_end) || t_end < t0)
+        return RD_E_INVALID;
+    if (trace_cap < 0 || (trace_cap > 0 && (!trace_h || !trace_iters || !trace_ok))) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    Desc d;
+    rd_status r = describe(prob, d);
+    if (r != RD_OK) return r;
+    if ((r = check_opts(opts)) != RD_OK) return r;
+    RD_CHECK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t fb = field_bytes(d.N, d.C, 8);
+    double *next = nullptr;
+    if (hipMalloc((void **)&next, fb) != hipSuccess) return RD_E_NOMEM;
+    std::memset(info, 0, sizeof(*info));
+    double t = t0, ht = a->ht0;
+    int rejects = 0, n = 0;
+    rd_status out = RD_OK;
+    while (!reached(t, t_end)) {
+        const double h = std::min(ht, t_end - t);
+        rd_info si;
+        r = rd_step(ctx, prob, opts, h, u, next, hip_stream, &si);
+        if (r == RD_E_INVALID || r == RD_E_DEVICE || r == RD_E_NOMEM) {
+            out = r;
+            break;
+        }
+        info->pdhg_iters += si.iters;
+        double nxt = h;
+        int32_t ok = 0;
+        rd_adapt_next(a, h, si.iters, si.status, &nxt, &ok);
+        if (n < trace_cap) {
+            trace_h[n] = h;
+            trace_iters[n] = si.iters;
+            trace_ok[n] = ok;
+        }
+        ++n;
+        if (ok) {
+            if (hipMemcpyAsync(u, next, fb, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+                out = RD_E_DEVICE;
+                break;
+            }
+            t = t + h;
+            ++info->accepted;
+            rejects = 0;
+        } else {
+            ++info->rejected;
+            ++rejects;
+        }
+        if (nxt < h) ++info->shrinks;
+        else if (nxt > h) ++info->enlarges;
+        ht = nxt;
+        if (!ok && (ht < a->ht_min || rejects > a->max_rejects)) {
+            out = RD_E_NOCONV;
+            break;
+        }
+    }
+    const bool synced = hipStreamSynchronize(st) == hipSuccess;
+    (void)hipFree(next);
+    if (!synced && out == RD_OK) out = RD_E_DEVICE;
+    info->t = t;
+    info->ht = ht;
+    info->status = out;
+    return out;
+}
+
 // ---------------------------------------------------------------- kernel-level entry points
 rd_status rd_residual(void *ctx, const rd_problem *prob, double h_t, const double *u, const double *uk, double *w,
                       void *hip_stream, double *res_l2) {

@@ -30,7 +30,8 @@ STATUS_NAMES = {RD_OK: "ok", RD_E_INVALID: "invalid", RD_E_NOCONV: "noconv", RD_
 # Every C-ABI symbol include/rd.h declares.
 EXPORTED = ("rd_create", "rd_destroy", "rd_default_opts", "rd_footprint_bytes", "rd_step", "rd_residual",
             "rd_precond_solve", "rd_prox", "rd_profile_iteration", "rd_serve_set_budget", "rd_traj_open", "rd_traj_submit",
-            "rd_serve_pump", "rd_poll", "rd_traj_read", "rd_traj_close", "rd_serve_stats", "rd_status_str")
+            "rd_serve_pump", "rd_poll", "rd_traj_read", "rd_traj_close", "rd_serve_stats", "rd_adapt_next",
+            "rd_advance", "rd_status_str")
 
 
 class Problem(ctypes.Structure):
@@ -64,6 +65,35 @@ class ServeInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Adapt(ctypes.Structure):
+    _fields_ = [("ht0", ctypes.c_double), ("eta", ctypes.c_double), ("n_hi", ctypes.c_int32), ("n_lo", ctypes.c_int32),
+                ("ht_min", ctypes.c_double), ("max_rejects", ctypes.c_int32), ("pad0", ctypes.c_int32)]
+
+
+class AdaptInfo(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int32), ("rejected", ctypes.c_int32), ("shrinks", ctypes.c_int32),
+                ("enlarges", ctypes.c_int32), ("pdhg_iters", ctypes.c_int64), ("t", ctypes.c_double),
+                ("ht", ctypes.c_double), ("status", ctypes.c_int32), ("pad0", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
+        d["status"] = STATUS_NAMES.get(self.status, str(self.status))
+        return d
+
+
+def make_adapt(ht0, eta=0.75, n_hi=100, n_lo=20, ht_min=1e-12, max_rejects=30):
+    return Adapt(ht0=float(ht0), eta=float(eta), n_hi=int(n_hi), n_lo=int(n_lo), ht_min=float(ht_min),
+                 max_rejects=int(max_rejects))
+
+
+def adapt_next(adapt, h, iters, status_code):
+    """The step-size rule (host logic of the library): (next h, accepted)."""
+    nxt, acc = ctypes.c_double(), ctypes.c_int32()
+    _check(_lib.rd_adapt_next(ctypes.byref(adapt), float(h), int(iters), int(status_code), ctypes.byref(nxt),
+                              ctypes.byref(acc)), "rd_adapt_next")
+    return nxt.value, bool(acc.value)
+
+
 _vp = ctypes.c_void_p
 _P = ctypes.POINTER
 _sig = {
@@ -85,6 +115,11 @@ _sig = {
     "rd_traj_read": (ctypes.c_int, [_vp, _vp, _vp]),
     "rd_traj_close": (ctypes.c_int, [_vp]),
     "rd_serve_stats": (ctypes.c_int, [_vp, _P(ServeInfo)]),
+    "rd_adapt_next": (ctypes.c_int, [_P(Adapt), ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                     _P(ctypes.c_double), _P(ctypes.c_int32)]),
+    "rd_advance": (ctypes.c_int, [_vp, _P(Problem), _P(Opts), _P(Adapt), ctypes.c_double, ctypes.c_double, _vp, _vp,
+                                  _P(AdaptInfo), _P(ctypes.c_double), _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                  ctypes.c_int32]),
     "rd_status_str": (ctypes.c_char_p, [ctypes.c_int]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -230,6 +265,20 @@ class Context:
         _check(_lib.rd_profile_iteration(self._h, ctypes.byref(problem), ctypes.byref(opts), float(ht), _dptr(u),
                                          int(reps), _stream_ptr(stream), out), "rd_profile_iteration")
         return dict(zip(("cols", "rowinv", "upd", "rowfwd"), list(out)))
+
+    def advance(self, u, t_end, problem, opts, adapt, t0=0.0, trace_cap=4096, stream=None):
+        """Advance u in place from t0 to t_end with the adaptive step-size rule.
+        Returns (info dict, trace list of (h, iterations, accepted))."""
+        info = AdaptInfo()
+        th = (ctypes.c_double * max(trace_cap, 1))()
+        ti = (ctypes.c_int32 * max(trace_cap, 1))()
+        tk = (ctypes.c_int32 * max(trace_cap, 1))()
+        code = _lib.rd_advance(self._h, ctypes.byref(problem), ctypes.byref(opts), ctypes.byref(adapt), float(t0),
+                               float(t_end), _dptr(u), _stream_ptr(stream), ctypes.byref(info), th, ti, tk,
+                               int(trace_cap))
+        _check(code, "rd_advance", allowed=(RD_OK, RD_E_NOCONV))
+        n = min(trace_cap, info.accepted + info.rejected)
+        return info.as_dict(), [(th[i], ti[i], bool(tk[i])) for i in range(n)]
 
     # ---------------------------------------------------------- serving
     def set_budget(self, nbytes):

@@ -661,6 +661,12 @@ template <typename T, int LOGN, int C> constexpr int col_jobs() {
     return cb1 >= 16 ? 16 : cb1 >= 8 ? 8 : cb1 >= 4 ? 4 : cb1 >= 2 ? 2 : 1;
 }
 template <typename T, int LOGN, int C> constexpr int col_threads() { return col_jobs<T, LOGN, C>() * ((1 << LOGN) / 16); }
+// Register budget: two column workgroups must fit on one CU (four SIMDs), so that
+// the extra decision workgroup of a launch that fills every CU starts at once.
+template <typename T, int LOGN, int C> constexpr int col_waves_per_eu() {
+    constexpr int w = 2 * col_threads<T, LOGN, C>() / 64 / 4;
+    return w < 1 ? 1 : w;
+}
 
 // FIN >= 0: the launch has one extra workgroup (the last) that takes the stop
 // decision of the preceding row pass of kind FIN, in parallel with the column
@@ -670,7 +676,7 @@ template <typename T, int LOGN, int C> constexpr int col_threads() { return col_
 constexpr int FIN_NONE = -1;
 
 template <typename T, int LOGN, int BC, int C, int FIN>
-__global__ __launch_bounds__((col_threads<T, LOGN, C>())) void k_cols(Slot *const *slots) {
+__global__ __launch_bounds__((col_threads<T, LOGN, C>()), (col_waves_per_eu<T, LOGN, C>())) void k_cols(Slot *const *slots) {
     constexpr int N = 1 << LOGN, H = N / 2;
     constexpr int NTH = col_threads<T, LOGN, C>();
     constexpr int CB = col_jobs<T, LOGN, C>();
@@ -689,8 +695,6 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>())) void k_cols(Slot *cons
     // blockIdx.x -> (component, first column); CB divides N/2
     const int c = blockIdx.x / (H / CB);
     const int kx0 = (blockIdx.x % (H / CB)) * CB;
-    Tw16<T, LOGN> twr;
-    load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
     cplx<T> *S = (cplx<T> *)s.S;
     // consecutive threads: rows of a tile, then columns, then tiles; every load of
     // the block is issued before any completes
@@ -714,9 +718,20 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>())) void k_cols(Slot *cons
     }
     __syncthreads();
     const cplx<T> *twd = (const cplx<T> *)s.twd;
-    wg_fft16<T, LOGN, -1, CB, NTH>(buf, twr);
+    {
+        Tw16<T, LOGN> twr;
+        load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
+        wg_fft16<T, LOGN, -1, CB, NTH>(buf, twr);
+    }
     cols_apply_symbol<T, LOGN, BC, CB, NTH>(buf, c * H + kx0, CB, s, twd);
-    wg_fft16<T, LOGN, +1, CB, NTH>(buf, twr);
+    // the inverse transform gathers its twiddles again rather than keeping the
+    // forward ones live across the symbol pass (register budget)
+    __asm__ volatile("" ::: "memory");
+    {
+        Tw16<T, LOGN> twr;
+        load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
+        wg_fft16<T, LOGN, +1, CB, NTH>(buf, twr);
+    }
 #pragma unroll
     for (int i = 0; i < (TOT + NTH - 1) / NTH; ++i) {
         const int idx = threadIdx.x + i * NTH;

@@ -202,11 +202,12 @@ def serving_leg(rd, torch, wl, n_traj, steps_per_traj):
 
 def adaptive_leg(ctx, rd, torch, cfg, u0):
     """The same trajectory with the adaptive step size of Sec. 2.2 (mixed precision):
-    h_t^0 = 4 h_t, eta = 0.75, N^* = 40, N_* = 15, over t in [0, 20 h_t]."""
+    h_t^0 = 50 h_t, eta = 0.75, N^* = 40, N_* = 15, over t in [0, 100 h_t]."""
     p = rd.problem_from_config(cfg)
     o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], omega=cfg["omega"], precision="mixed")
-    a = rd.make_adapt(4 * cfg["ht"], 0.75, 40, 15)
-    t_end = 20 * cfg["ht"]
+    ht0 = 50 * cfg["ht"]
+    a = rd.make_adapt(ht0, 0.75, 40, 15)
+    t_end = 100 * cfg["ht"]
     u = u0.clone()
     ctx.advance(u, 2 * cfg["ht"], p, o, a)   # warm: workspaces and tables
     u.copy_(u0)
@@ -215,7 +216,7 @@ def adaptive_leg(ctx, rd, torch, cfg, u0):
     info, trace = ctx.advance(u, t_end, p, o, a)
     wall = time.perf_counter() - t0
     N = cfg["N"]
-    return dict(t_end=t_end, ht0=4 * cfg["ht"], eta=0.75, n_hi=40, n_lo=15, wall_s=wall,
+    return dict(t_end=t_end, ht0=ht0, eta=0.75, n_hi=40, n_lo=15, wall_s=wall,
                 pt_iters_per_s=N * N * info["pdhg_iters"] / wall, **info,
                 step_sizes=sorted(set(round(h, 12) for h, _, ok in trace if ok)))
 
@@ -283,7 +284,7 @@ def main():
                     frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None if traffic is None else round(traffic),
                     traffic_unit="bytes per launch", bytes_per_launch=dk["bytes"], ms_per_launch=dk["ms"])
 
-    log("adaptive step size: mixed, t in [0, %g]" % (20 * cfg["ht"]))
+    log("adaptive step size: mixed, t in [0, %g]" % (100 * cfg["ht"]))
     adaptive = adaptive_leg(ctx, rd, torch, cfg, u0)
     log("  %s" % json.dumps(adaptive))
 

@@ -17,6 +17,13 @@ equation is the root of ``F(U) = 0`` (Sec. 2.1, eq. 12).  The equations:
 * ``schnakenberg`` (Sec. 3.4.1, eqs. 35-36), U = (u, v):
   F_u = U - U^k - h_t (D1 Lap U + kappa (a - U + U^2 V))
   F_v = V - V^k - h_t (D2 Lap V + kappa (b - U^2 V))
+* ``fch`` (Sec. 3.3, the sixth-order functionalized Cahn-Hilliard equation),
+  u_t = Lap (eps^2 Lap - W2(u) + eps^2) (eps^2 Lap u - W1(u)), W = (u^2 - 1)^2 / 4,
+  F(U) = U - U^k - h_t Lap (eps^2 Lap - diag W2(U) + eps^2 I)(eps^2 Lap U - W1(U)),
+  with ``diff[0] = eps^2`` and W1, W2, W3 the first three derivatives of W.  The
+  paper states W2(u) = 3u^2; with its W, W1(u) = u^3 - u and W2(u) = 3u^2 - 1
+  (which is the value 2 at u = +-1 that the paper's preconditioner uses); this
+  reading is taken.
 
 ``adjoint(U, P~)`` is ``grad F(U)^T P~``, the vector the U-update of the G-prox
 PDHG dynamic subtracts (eqs. 23, 32 and the Schnakenberg update of Sec. 3.4.1).
@@ -34,7 +41,8 @@ CAHN_HILLIARD = "cahn_hilliard"
 SCHNAKENBERG = "schnakenberg"
 HEAT = "heat"
 BIHARMONIC = "biharmonic"
-KINDS = (ALLEN_CAHN, CAHN_HILLIARD, SCHNAKENBERG, HEAT, BIHARMONIC)
+FCH = "fch"
+KINDS = (ALLEN_CAHN, CAHN_HILLIARD, SCHNAKENBERG, HEAT, BIHARMONIC, FCH)
 
 
 @dataclass
@@ -92,6 +100,21 @@ def chem_potential_ch_prime(u, b):
     return b * (3.0 * u * u - 1.0)
 
 
+def fch_w1(u):
+    """W1(u) = W'(u) = u^3 - u."""
+    return u * u * u - u
+
+
+def fch_w2(u):
+    """W2(u) = 3 u^2 - 1."""
+    return 3.0 * u * u - 1.0
+
+
+def fch_w3(u):
+    """W3(u) = 6 u."""
+    return 6.0 * u
+
+
 def F(prob, U, Uk, ht):
     """The step residual F(U); shape (N, N), or (2, N, N) for Schnakenberg."""
     h, bc, k = prob.h, prob.bc, prob.kind
@@ -104,6 +127,11 @@ def F(prob, U, Uk, ht):
                 - ht * grid.lap5(chem_potential_ch(U, prob.b), h, bc))
     if k == BIHARMONIC:
         return U - Uk + prob.lam * ht * grid.lap13(U, h, bc)
+    if k == FCH:
+        e2 = prob.lam
+        mu = e2 * grid.lap5(U, h, bc) - fch_w1(U)
+        nu = e2 * grid.lap5(mu, h, bc) - fch_w2(U) * mu + e2 * mu
+        return U - Uk - ht * grid.lap5(nu, h, bc)
     if k == SCHNAKENBERG:
         u, v = U[0], U[1]
         d1, d2 = prob.diff
@@ -126,6 +154,15 @@ def adjoint(prob, U, Pt, ht):
                 - ht * chem_potential_ch_prime(U, prob.b) * grid.lap5(Pt, h, bc))
     if k == BIHARMONIC:
         return Pt + prob.lam * ht * grid.lap13(Pt, h, bc)
+    if k == FCH:
+        # grad F^T = I - h_t [(eps^2 Lap - D)(eps^2 Lap - D + eps^2) - diag(W3(U) B)] Lap,
+        # D = diag W2(U), B = eps^2 Lap U - W1(U)
+        e2 = prob.lam
+        D = fch_w2(U)
+        B = e2 * grid.lap5(U, h, bc) - fch_w1(U)
+        q = grid.lap5(Pt, h, bc)
+        a = e2 * grid.lap5(q, h, bc) - D * q + e2 * q
+        return Pt - ht * (e2 * grid.lap5(a, h, bc) - D * a) + ht * fch_w3(U) * B * q
     if k == SCHNAKENBERG:
         u, v = U[0], U[1]
         p, q = Pt[0], Pt[1]
@@ -138,19 +175,24 @@ def adjoint(prob, U, Pt, ht):
 
 
 def precond_coeffs(prob, ht):
-    """Per-component (alpha, beta) of G = (I - alpha Lap + beta Lap^2)^2.
+    """Per-component (alpha, beta, gamma) of G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2.
 
     Allen-Cahn / heat: G = (I - lambda h_t Lap)^2 (Sec. 2.1).
     Cahn-Hilliard / biharmonic: G = (I + lambda h_t Lap Lap)^2 (Sec. 3.2, sign as in F).
     Schnakenberg: G_u = (I - h_t D1 Lap)^2, G_v = (I - h_t D2 Lap)^2 (Sec. 3.4.1).
+    FCH: G = (I - h_t eps^2 Lap (eps^2 Lap - (2 - eps^2) I) Lap)^2 (Sec. 3.3: W2 replaced
+    by its value 2 at the wells), i.e. beta = h_t eps^2 (2 - eps^2), gamma = h_t eps^4.
     """
     k = prob.kind
     if k in (ALLEN_CAHN, HEAT):
-        return [(prob.lam * ht, 0.0)]
+        return [(prob.lam * ht, 0.0, 0.0)]
     if k in (CAHN_HILLIARD, BIHARMONIC):
-        return [(0.0, prob.lam * ht)]
+        return [(0.0, prob.lam * ht, 0.0)]
+    if k == FCH:
+        e2 = prob.lam
+        return [(0.0, ht * e2 * (2.0 - e2), ht * e2 * e2)]
     if k == SCHNAKENBERG:
-        return [(prob.diff[0] * ht, 0.0), (prob.diff[1] * ht, 0.0)]
+        return [(prob.diff[0] * ht, 0.0, 0.0), (prob.diff[1] * ht, 0.0, 0.0)]
     raise ValueError(k)
 
 
@@ -179,6 +221,13 @@ def jacobian(prob, U, ht):
                 - ht * (Lm @ sp.diags(chem_potential_ch_prime(U, prob.b).ravel()))).tocsr()
     if k == BIHARMONIC:
         return (I + prob.lam * ht * (Lm @ Lm)).tocsr()
+    if k == FCH:
+        e2 = prob.lam
+        u = U.ravel()
+        D = sp.diags(fch_w2(u))
+        B = e2 * (Lm @ u) - fch_w1(u)
+        A = e2 * Lm - D + e2 * I
+        return (I - ht * (Lm @ (A @ (e2 * Lm - D) - sp.diags(fch_w3(u) * B)))).tocsr()
     if k == SCHNAKENBERG:
         u, v = U[0].ravel(), U[1].ravel()
         d1, d2 = prob.diff

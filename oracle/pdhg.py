@@ -61,8 +61,7 @@ def precond_apply(prob, W, ht, precond=True):
         return np.array(W, copy=True)
     coeffs = eq.precond_coeffs(prob, ht)
     if prob.ncomp == 1:
-        a, b = coeffs[0]
-        return spectral.precond_solve(W, prob.h, prob.bc, a, b)
+        return spectral.precond_solve(W, prob.h, prob.bc, *coeffs[0])
     return np.stack([spectral.precond_solve(W[c], prob.h, prob.bc, *coeffs[c])
                      for c in range(prob.ncomp)])
 

@@ -8,6 +8,9 @@ in the 5-point Laplacian, so
 
 with (alpha, beta) = (lambda h_t, 0) for Allen-Cahn / heat / each Schnakenberg
 component (``D_i h_t``), and (0, lambda h_t) for Cahn-Hilliard / biharmonic.
+For the sixth-order FCH equation (Sec. 3.3) a cubic term enters,
+``G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2`` with symbol
+``(1 + alpha mu + beta mu^2 + gamma mu^3)^2``.
 ``G`` is diagonalised by the 2-D DFT for periodic grids (Sec. 2.1, "Application of
 FFT") and by the 2-D DCT-II for Neumann grids (Remark 1).  With ``mu`` the
 eigenvalue of ``-Lap`` the symbol is ``g = (1 + alpha mu + beta mu^2)^2``.
@@ -42,10 +45,10 @@ def laplacian_symbol(N, h, bc):
     return s[:, None] + s[None, :]
 
 
-def precond_symbol(N, h, bc, alpha, beta):
-    """Eigenvalues of ``G = (I - alpha Lap + beta Lap^2)^2`` on the 2-D grid."""
+def precond_symbol(N, h, bc, alpha, beta, gamma=0.0):
+    """Eigenvalues of ``G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2`` on the 2-D grid."""
     mu = laplacian_symbol(N, h, bc)
-    return (1.0 + alpha * mu + beta * mu * mu) ** 2
+    return (1.0 + alpha * mu + beta * mu * mu + gamma * mu * mu * mu) ** 2
 
 
 def forward_transform(w, bc):
@@ -66,20 +69,20 @@ def inverse_transform(what, bc):
     raise ValueError(bc)
 
 
-def precond_solve(w, h, bc, alpha, beta):
+def precond_solve(w, h, bc, alpha, beta, gamma=0.0):
     """``Y = G^-1 W``: transform, divide by the symbol, transform back.
 
     This is the step "Solve G Y_n = W_n via 2D FFT (DCT)" of Algorithm 1.
     """
     N = w.shape[0]
-    g = precond_symbol(N, h, bc, alpha, beta)
+    g = precond_symbol(N, h, bc, alpha, beta, gamma)
     return inverse_transform(forward_transform(w, bc) / g, bc)
 
 
-def precond_matrix(N, h, bc, alpha, beta):
+def precond_matrix(N, h, bc, alpha, beta, gamma=0.0):
     """Dense ``G`` assembled from the sparse Laplacian matrix (for pins on small grids)."""
     Lm = grid.lap5_matrix(N, h, bc).toarray()
-    A = np.eye(N * N) - alpha * Lm + beta * (Lm @ Lm)
+    A = np.eye(N * N) - alpha * Lm + beta * (Lm @ Lm) - gamma * (Lm @ Lm @ Lm)
     return A @ A
 
 

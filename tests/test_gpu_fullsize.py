@@ -38,8 +38,7 @@ def test_precond_solve_large(ctx, rd, N, bc, precision):
     op = oracle_problem(cfg)
     ht = cfg["ht"]
     W = np.random.default_rng(N).standard_normal((N, N))
-    a, b = oeq.precond_coeffs(op, ht)[0]
-    Y_ref = ospec.precond_solve(W, op.h, bc, a, b)
+    Y_ref = ospec.precond_solve(W, op.h, bc, *oeq.precond_coeffs(op, ht)[0])
     Y = ctx.precond_solve(dev(W), ht, rd.problem_from_config(cfg), precision).cpu().numpy()
     bar = 1e-12 * np.max(np.abs(Y_ref)) if precision == "fp64" else 2e-6 * np.max(np.abs(W))
     assert max_abs(Y, Y_ref) <= bar

@@ -53,20 +53,25 @@ typedef enum { RD_BC_PERIODIC = 0, RD_BC_NEUMANN = 1 } rd_bc;
 
 /* Linear operator of F.  RD_OP_LAP5: +lambda Lap with the 5-point Laplacian (Sec. 2.1;
  * periodic block-circulant form, or the Neumann L_1/L_2 form of Remark 1, eq. 24).
- * RD_OP_BIHARM13: -lambda Lap Lap with the 13-point stencil (= 5-point squared; Sec. 3.2). */
-typedef enum { RD_OP_LAP5 = 0, RD_OP_BIHARM13 = 1 } rd_operator;
+ * RD_OP_BIHARM13: -lambda Lap Lap with the 13-point stencil (= 5-point squared; Sec. 3.2).
+ * RD_OP_FCH6: the sixth-order functionalized Cahn-Hilliard operator of Sec. 3.3 (nested
+ * 5-point Laplacians, 25-point reach), with RD_RX_FCH only; FP64 precision only.        */
+typedef enum { RD_OP_LAP5 = 0, RD_OP_BIHARM13 = 1, RD_OP_FCH6 = 2 } rd_operator;
 
 /* Reaction term.  Parameters in rd_problem.p[]:
  *   RD_RX_NONE          linear step (heat with LAP5, biharmonic with BIHARM13)
  *   RD_RX_ALLEN_CAHN    p[0] = b:  f(u) = b (u - u^3)           (Sec. 3.1, eq. 25), LAP5 only
  *   RD_RX_CAHN_HILLIARD p[0] = b:  + Lap (b (u^3 - u))          (Sec. 3.2, eq. 28), BIHARM13 only
  *   RD_RX_SCHNAKENBERG  p[0] = a, p[1] = b, p[2] = kappa; two components (u, v) with
- *                       diffusion diff[0], diff[1]                (Sec. 3.4.1), LAP5 only      */
+ *                       diffusion diff[0], diff[1]                (Sec. 3.4.1), LAP5 only
+ *   RD_RX_FCH           u_t = Lap (eps^2 Lap - W''(u) + eps^2)(eps^2 Lap u - W'(u)),
+ *                       W = (u^2 - 1)^2 / 4, diff[0] = eps^2      (Sec. 3.3), FCH6 only     */
 typedef enum {
     RD_RX_NONE = 0,
     RD_RX_ALLEN_CAHN = 1,
     RD_RX_CAHN_HILLIARD = 2,
-    RD_RX_SCHNAKENBERG = 3
+    RD_RX_SCHNAKENBERG = 3,
+    RD_RX_FCH = 4
 } rd_reaction_kind;
 
 typedef struct {

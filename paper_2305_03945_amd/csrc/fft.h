@@ -200,11 +200,12 @@ __device__ __forceinline__ void rows_pre_inverse(cplx<T> *buf, const cplx<T> *__
     __syncthreads();
 }
 
-// Symbol multiplier 1 / (N^2 g), g = (1 + alpha mu + beta mu^2)^2, mu = s_kx + s_ky.
+// Symbol multiplier 1 / (N^2 g), g = (1 + alpha mu + beta mu^2 + gamma mu^3)^2,
+// mu = s_kx + s_ky.
 __device__ __forceinline__ double symbol_mult(const double *__restrict__ eig, int kx, int ky, double alpha,
-                                              double beta, double invN2) {
+                                              double beta, double gamma, double invN2) {
     const double mu = eig[kx] + eig[ky];
-    const double a = 1.0 + alpha * mu + beta * mu * mu;
+    const double a = 1.0 + mu * (alpha + mu * (beta + gamma * mu));
     return invN2 / (a * a);
 }
 
@@ -229,26 +230,26 @@ __device__ __forceinline__ void cols_apply_symbol(cplx<T> *buf, int job0, int nj
         if (reg >= njobs) continue;
         const int job = job0 + reg;
         const int c = job / H, j = job % H;
-        const double al = s.alpha[c], be = s.beta[c];
+        const double al = s.alpha[c], be = s.beta[c], ga = s.gamma[c];
         const int nl = (l == 0) ? H : N - l;
         cplx<T> &zlr = buf[rix<LOGN>(reg, l)];
         cplx<T> &znr = buf[rix<LOGN>(reg, nl)];
         const cplx<T> zl = zlr, zn = znr;
         if constexpr (BC == BC_P) {
             if (j > 0) {
-                const T m1 = (T)symbol_mult(s.eig, j, l, al, be, invN2);
-                const T m2 = (T)symbol_mult(s.eig, j, nl, al, be, invN2);
+                const T m1 = (T)symbol_mult(s.eig, j, l, al, be, ga, invN2);
+                const T m2 = (T)symbol_mult(s.eig, j, nl, al, be, ga, invN2);
                 zlr = {zl.re * m1, zl.im * m1};
                 znr = {zn.re * m2, zn.im * m2};
             } else if (l == 0) {
                 // bins 0 and N/2 of the packed (kx = 0, kx = N/2) column: real pairs
-                zlr = {zl.re * (T)symbol_mult(s.eig, 0, 0, al, be, invN2),
-                       zl.im * (T)symbol_mult(s.eig, H, 0, al, be, invN2)};
-                znr = {zn.re * (T)symbol_mult(s.eig, 0, H, al, be, invN2),
-                       zn.im * (T)symbol_mult(s.eig, H, H, al, be, invN2)};
+                zlr = {zl.re * (T)symbol_mult(s.eig, 0, 0, al, be, ga, invN2),
+                       zl.im * (T)symbol_mult(s.eig, H, 0, al, be, ga, invN2)};
+                znr = {zn.re * (T)symbol_mult(s.eig, 0, H, al, be, ga, invN2),
+                       zn.im * (T)symbol_mult(s.eig, H, H, al, be, ga, invN2)};
             } else {
-                const T ma = (T)symbol_mult(s.eig, 0, l, al, be, invN2);
-                const T mb = (T)symbol_mult(s.eig, H, l, al, be, invN2);
+                const T ma = (T)symbol_mult(s.eig, 0, l, al, be, ga, invN2);
+                const T mb = (T)symbol_mult(s.eig, H, l, al, be, ga, invN2);
                 cplx<T> A = {(zl.re + zn.re) * (T)0.5, (zl.im - zn.im) * (T)0.5};
                 cplx<T> B = {(zl.im + zn.im) * (T)0.5, (zn.re - zl.re) * (T)0.5};
                 A = {A.re * ma, A.im * ma};
@@ -259,20 +260,20 @@ __device__ __forceinline__ void cols_apply_symbol(cplx<T> *buf, int job0, int nj
         } else {
             const int ka = 2 * j, kb = 2 * j + 1;
             if (l == 0) {
-                zlr = {zl.re * (T)symbol_mult(s.eig, ka, 0, al, be, invN2),
-                       zl.im * (T)symbol_mult(s.eig, kb, 0, al, be, invN2)};
-                znr = {zn.re * (T)symbol_mult(s.eig, ka, H, al, be, invN2),
-                       zn.im * (T)symbol_mult(s.eig, kb, H, al, be, invN2)};
+                zlr = {zl.re * (T)symbol_mult(s.eig, ka, 0, al, be, ga, invN2),
+                       zl.im * (T)symbol_mult(s.eig, kb, 0, al, be, ga, invN2)};
+                znr = {zn.re * (T)symbol_mult(s.eig, ka, H, al, be, ga, invN2),
+                       zn.im * (T)symbol_mult(s.eig, kb, H, al, be, ga, invN2)};
             } else {
                 const cplx<T> w = twd[l];
                 const cplx<T> A = {(zl.re + zn.re) * (T)0.5, (zl.im - zn.im) * (T)0.5};
                 const cplx<T> B = {(zl.im + zn.im) * (T)0.5, (zn.re - zl.re) * (T)0.5};
                 const cplx<T> qa = cmul(A, w), qb = cmul(B, w);
                 // cosine coefficients at l and N-l, scaled by their symbols
-                const T xal = qa.re * (T)symbol_mult(s.eig, ka, l, al, be, invN2);
-                const T xan = -qa.im * (T)symbol_mult(s.eig, ka, N - l, al, be, invN2);
-                const T xbl = qb.re * (T)symbol_mult(s.eig, kb, l, al, be, invN2);
-                const T xbn = -qb.im * (T)symbol_mult(s.eig, kb, N - l, al, be, invN2);
+                const T xal = qa.re * (T)symbol_mult(s.eig, ka, l, al, be, ga, invN2);
+                const T xan = -qa.im * (T)symbol_mult(s.eig, ka, N - l, al, be, ga, invN2);
+                const T xbl = qb.re * (T)symbol_mult(s.eig, kb, l, al, be, ga, invN2);
+                const T xbn = -qb.im * (T)symbol_mult(s.eig, kb, N - l, al, be, ga, invN2);
                 const cplx<T> wc = cconj(w);
                 const cplx<T> va = cmul(wc, cplx<T>{xal, -xan});
                 const cplx<T> vb = cmul(wc, cplx<T>{xbl, -xbn});

@@ -84,6 +84,27 @@ __device__ __forceinline__ void eval_F(SlotRef s, Acc u, const V *ukc, V *W, V *
         const V lapg = (g(ul) + g(ur) + g(uu) + g(ud) - (V)4 * g(u0)) * ih2;
         W[0] = u0 - ukc[0] + (V)s.diff[0] * ht * lap13 - ht * lapg;
         Uc[0] = u0;
+    } else if constexpr (EQ == EQ_FCH) {
+        // Sec. 3.3: mu = eps^2 Lap U - W1(U), nu = eps^2 Lap mu - W2(U) mu + eps^2 mu,
+        // F = U - U^k - h_t Lap nu; W1 = u^3 - u, W2 = 3u^2 - 1.  Evaluated from U on
+        // the 25-point neighbourhood (the compiler shares the repeated sub-terms).
+        const V e2 = (V)s.diff[0];
+        auto lapu = [&](int dy, int dx) {
+            return (u(0, dy, dx - 1) + u(0, dy, dx + 1) + u(0, dy - 1, dx) + u(0, dy + 1, dx) - (V)4 * u(0, dy, dx)) * ih2;
+        };
+        auto mu = [&](int dy, int dx) {
+            const V v = u(0, dy, dx);
+            return e2 * lapu(dy, dx) - (v * v * v - v);
+        };
+        auto nu = [&](int dy, int dx) {
+            const V v = u(0, dy, dx), m = mu(dy, dx);
+            const V lapm = (mu(dy, dx - 1) + mu(dy, dx + 1) + mu(dy - 1, dx) + mu(dy + 1, dx) - (V)4 * m) * ih2;
+            return e2 * lapm - ((V)3 * v * v - (V)1) * m + e2 * m;
+        };
+        const V lapnu = (nu(0, -1) + nu(0, 1) + nu(-1, 0) + nu(1, 0) - (V)4 * nu(0, 0)) * ih2;
+        const V u0 = u(0, 0, 0);
+        W[0] = u0 - ukc[0] - ht * lapnu;
+        Uc[0] = u0;
     } else {
         const V u0 = u(0, 0, 0), v0 = u(1, 0, 0);
         const V lu = (u(0, 0, -1) + u(0, 0, 1) + u(0, -1, 0) + u(0, 1, 0) - (V)4 * u0) * ih2;
@@ -164,6 +185,28 @@ __device__ __forceinline__ void eval_adjoint(SlotRef s, Acc p, const V *Uc, V *o
     }
 }
 
+// grad F(U)^T P~ of the FCH step (Sec. 3.3): with q = Lap P~, D = W2(U),
+// B = eps^2 Lap U - W1(U):
+//   out = P~ - h_t (eps^2 Lap - D)(eps^2 Lap - D + eps^2) q + h_t W3(U) B q.
+// p: accessor of P~ (25-point reach), u: accessor of U (5-point reach).
+template <typename V, class AccP, class AccU>
+__device__ __forceinline__ V eval_adjoint_fch(SlotRef s, AccP p, AccU u) {
+    const V ht = (V)s.ht, ih2 = (V)s.inv_h2, e2 = (V)s.diff[0];
+    auto q = [&](int dy, int dx) {
+        return (p(0, dy, dx - 1) + p(0, dy, dx + 1) + p(0, dy - 1, dx) + p(0, dy + 1, dx) - (V)4 * p(0, dy, dx)) * ih2;
+    };
+    auto a = [&](int dy, int dx) {
+        const V v = u(0, dy, dx), qq = q(dy, dx);
+        const V lapq = (q(dy, dx - 1) + q(dy, dx + 1) + q(dy - 1, dx) + q(dy + 1, dx) - (V)4 * qq) * ih2;
+        return e2 * lapq - ((V)3 * v * v - (V)1) * qq + e2 * qq;
+    };
+    const V u0 = u(0, 0, 0), a0 = a(0, 0);
+    const V lapa = (a(0, -1) + a(0, 1) + a(-1, 0) + a(1, 0) - (V)4 * a0) * ih2;
+    const V lapu = (u(0, 0, -1) + u(0, 0, 1) + u(0, -1, 0) + u(0, 1, 0) - (V)4 * u0) * ih2;
+    const V B = e2 * lapu - (u0 * u0 * u0 - u0);
+    return p(0, 0, 0) - ht * (e2 * lapa - ((V)3 * u0 * u0 - (V)1) * a0) + ht * ((V)6 * u0) * B * q(0, 0);
+}
+
 // ---------------------------------------------------------------- stencil windows
 // Four consecutive points (y, x0 .. x0+3) of one row, x0 a multiple of 4, with
 // the stencil neighbourhood they need: row y + dy holds x0 - hx .. x0 + 3 + hx,
@@ -202,7 +245,7 @@ template <typename T> __device__ __forceinline__ void store4(gptr_t<T> p, const 
     *(gptr_t<vec4_t<T>>)p = v;
 }
 
-template <int EQ> constexpr int stencil_hy() { return EQ == EQ_BIH ? 2 : 1; }
+template <int EQ> constexpr int stencil_hy() { return EQ == EQ_FCH ? 3 : EQ == EQ_BIH ? 2 : 1; }
 
 // ---------------------------------------------------------------- deterministic block sums
 template <int K> __device__ __forceinline__ void block_sum(double *v, double *scratch /* K * NT/64 */) {
@@ -842,6 +885,20 @@ __global__ __launch_bounds__(NT) void k_upd(Slot *const *slots) {
     Win<T, HY> wp[C];
     vec4_t<T> un[C];
     T Uc[UPD_PPT][C];
+    if constexpr (EQ == EQ_FCH) {
+        // the FCH adjoint also needs U on the 5-point neighbourhood (FP64 path only)
+        Win<T, 1> wu;
+        load_win<T, BC, LOGN, HY>(wp[0], Pt, y, x0);
+        load_win<T, BC, LOGN, 1>(wu, Ucur, y, x0);
+        const T tu = (T)s.tau_u;
+        vec4_t<T> o;
+#pragma unroll
+        for (int k = 0; k < UPD_PPT; ++k)
+            o[k] = wu.at(k, 0, 0) - tu * eval_adjoint_fch<T>(s, [&](int, int dy, int dx) { return wp[0].at(k, dy, dx); },
+                                                             [&](int, int dy, int dx) { return wu.at(k, dy, dx); });
+        store4<T>(Unext + g0, o);
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         load_win<T, BC, LOGN, HY>(wp[c], Pt + c * NN, y, x0);

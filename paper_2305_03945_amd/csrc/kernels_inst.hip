@@ -82,6 +82,8 @@ void launch_tout(Slot *const *slots, int nslots, const double *, double *out, hi
                        slots, out);
 }
 
+template <int BC, int EQ> void fill_mixed();
+
 template <int BC, int EQ> void fill() {
     KSet &f = g_kernels[MODE_F64][L][BC][EQ];
     f.init = launch_rowfwd_fin<double, BC, EQ, K_INIT64>;
@@ -94,6 +96,11 @@ template <int BC, int EQ> void fill() {
     f.tin = launch_tin<double, BC, EQ>;
     f.tout = launch_tout<double, BC, EQ>;
     f.rows_per_block = row_block<double, EQ>();
+    // The FCH equation has no mixed-precision form (FP64 only).
+    if constexpr (EQ != EQ_FCH) fill_mixed<BC, EQ>();
+}
+
+template <int BC, int EQ> void fill_mixed() {
     KSet &m = g_kernels[MODE_MIXED][L][BC][EQ];
     m.init = launch_rowfwd_fin<float, BC, EQ, K_OUTER_INIT>;
     m.outer = launch_rowfwd_fin<float, BC, EQ, K_OUTER_UPD>;
@@ -119,6 +126,8 @@ void RD_CAT(register_logn_, RD_LOGN)() {
     fill<BC_N, EQ_LAP5>();
     fill<BC_N, EQ_BIH>();
     fill<BC_N, EQ_SCHNAK>();
+    fill<BC_P, EQ_FCH>();
+    fill<BC_N, EQ_FCH>();
 }
 
 }  // namespace rdk

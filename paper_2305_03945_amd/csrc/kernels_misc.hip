@@ -16,10 +16,12 @@ void launch_residual(int bc, int eq, const Slot *slot_dev, int N, const double *
     if (bc == BC_P) {
         if (eq == EQ_LAP5) RD_RES(BC_P, EQ_LAP5);
         else if (eq == EQ_BIH) RD_RES(BC_P, EQ_BIH);
+        else if (eq == EQ_FCH) RD_RES(BC_P, EQ_FCH);
         else RD_RES(BC_P, EQ_SCHNAK);
     } else {
         if (eq == EQ_LAP5) RD_RES(BC_N, EQ_LAP5);
         else if (eq == EQ_BIH) RD_RES(BC_N, EQ_BIH);
+        else if (eq == EQ_FCH) RD_RES(BC_N, EQ_FCH);
         else RD_RES(BC_N, EQ_SCHNAK);
     }
 #undef RD_RES

@@ -16,7 +16,9 @@ namespace rdk {
 //   EQ_LAP5   : +lambda Lap (5-point) with the Allen-Cahn reaction (b = 0: heat)
 //   EQ_BIH    : -lambda Lap Lap (13-point) with + Lap g(u) (b = 0: biharmonic)
 //   EQ_SCHNAK : two components, 5-point Laplacians, Schnakenberg kinetics
-enum { EQ_LAP5 = 0, EQ_BIH = 1, EQ_SCHNAK = 2, EQ_COUNT = 3 };
+//   EQ_FCH    : sixth-order functionalized Cahn-Hilliard (nested 5-point Laplacians,
+//               25-point reach), FP64 only
+enum { EQ_LAP5 = 0, EQ_BIH = 1, EQ_SCHNAK = 2, EQ_FCH = 3, EQ_COUNT = 4 };
 enum { BC_P = 0, BC_N = 1 };
 // Precision mode of a step: plain FP64 iteration, or FP32 inner iteration on a
 // correction with FP64 outer residual passes.
@@ -65,7 +67,8 @@ struct Slot {
     double b;                    // Allen-Cahn / Cahn-Hilliard reaction coefficient
     double sa, sb, kappa;        // Schnakenberg a, b, kappa
     double tau_u, tau_p, omega, tol, inner_rtol;
-    double alpha[2], beta[2];    // G = (I - alpha Lap + beta Lap^2)^2 per component
+    double alpha[2], beta[2];    // G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2 per component
+    double gamma[2];
     // Iterate buffers, element type T of the PDHG loop (double for FP64, float for
     // the mixed inner loop), each [ncomp][N][N]:
     void *U[2];                  // FP64: U_n ping-pong; mixed: correction e_n ping-pong

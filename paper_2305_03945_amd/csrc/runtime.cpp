@@ -75,6 +75,9 @@ rd_status describe(const rd_problem *p, Desc &d) {
     } else if (p->op == RD_OP_BIHARM13 && (p->rx == RD_RX_NONE || p->rx == RD_RX_CAHN_HILLIARD)) {
         d.eq = EQ_BIH;
         d.C = 1;
+    } else if (p->op == RD_OP_FCH6 && p->rx == RD_RX_FCH) {
+        d.eq = EQ_FCH;
+        d.C = 1;
     } else if (p->op == RD_OP_LAP5 && p->rx == RD_RX_SCHNAKENBERG) {
         d.eq = EQ_SCHNAK;
         d.C = 2;
@@ -331,14 +334,20 @@ void fill_params(Slot &s, const rd_problem *p, const rd_opts *o, const Desc &d, 
         s.tol = o->tol;
         s.inner_rtol = o->inner_rtol;
     }
-    // G = (I - alpha Lap + beta Lap^2)^2 per component
+    // G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2 per component
     for (int c = 0; c < 2; ++c) {
         s.alpha[c] = 0.0;
         s.beta[c] = 0.0;
+        s.gamma[c] = 0.0;
     }
     if (d.eq == EQ_LAP5) s.alpha[0] = p->diff[0] * ht;
     else if (d.eq == EQ_BIH) s.beta[0] = p->diff[0] * ht;
-    else {
+    else if (d.eq == EQ_FCH) {
+        // Sec. 3.3: G = (I - h_t eps^2 Lap (eps^2 Lap - (2 - eps^2)) Lap)^2, eps^2 = diff[0]
+        const double e2 = p->diff[0];
+        s.beta[0] = ht * e2 * (2.0 - e2);
+        s.gamma[0] = ht * e2 * e2;
+    } else {
         s.alpha[0] = p->diff[0] * ht;
         s.alpha[1] = p->diff[1] * ht;
     }
@@ -543,6 +552,7 @@ size_t rd_footprint_bytes(const rd_problem *prob, const rd_opts *opts) {
     if (describe(prob, d) != RD_OK || check_opts(opts) != RD_OK) return 0;
     std::call_once(g_register_once, register_all);
     const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
+    if (!g_kernels[mode][d.logN][d.bc][d.eq].init) return 0;   // no such precision for the equation
     const int rpb = g_kernels[mode][d.logN][d.bc][d.eq].rows_per_block;
     // resident trajectory state + the step workspace
     return workspace_bytes(d.N, d.C, mode, rpb) + field_bytes(d.N, d.C, 8);
@@ -561,6 +571,7 @@ rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double
     hipStream_t st = (hipStream_t)hip_stream;
     const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
     const KSet &k = g_kernels[mode][d.logN][d.bc][d.eq];
+    if (!k.init) return RD_E_INVALID;   // no such precision for the equation
     Tables *t = nullptr;
     if ((r = get_tables(c, d.N, d.bc, d.h, t)) != RD_OK) return r;
     Workspace *w = nullptr;
@@ -592,6 +603,7 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
     hipStream_t st = (hipStream_t)hip_stream;
     const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
     const KSet &k = g_kernels[mode][d.logN][d.bc][d.eq];
+    if (!k.init) return RD_E_INVALID;   // no such precision for the equation
     Tables *t = nullptr;
     if ((r = get_tables(c, d.N, d.bc, d.h, t)) != RD_OK) return r;
     Workspace *w = nullptr;
@@ -803,6 +815,7 @@ rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_
     hipStream_t st = (hipStream_t)hip_stream;
     const int mode = precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
     const KSet &k = g_kernels[mode][d.logN][d.bc][d.eq];
+    if (!k.tin) return RD_E_INVALID;   // no such precision for the equation
     Tables *t = nullptr;
     if ((r = get_tables(c, d.N, d.bc, d.h, t)) != RD_OK) return r;
     Workspace *w = nullptr;
@@ -862,6 +875,10 @@ rd_status rd_traj_open(void *ctx, const rd_problem *prob, const rd_opts *opts, c
     t->opts = *opts;
     t->d = d;
     t->d.mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
+    if (!g_kernels[t->d.mode][d.logN][d.bc][d.eq].init) {   // no such precision for the equation
+        delete t;
+        return RD_E_INVALID;
+    }
     const size_t fb = field_bytes(d.N, d.C, 8);
     if (hipMalloc((void **)&t->u, fb) != hipSuccess) {
         delete t;

@@ -19,8 +19,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---------------------------------------------------------------- enums (values of rd.h)
 RD_OK, RD_E_INVALID, RD_E_NOCONV, RD_E_NONFINITE, RD_E_NOMEM, RD_E_DEVICE, RD_E_BUSY = 0, -1, -2, -3, -4, -5, -6
 RD_BC_PERIODIC, RD_BC_NEUMANN = 0, 1
-RD_OP_LAP5, RD_OP_BIHARM13 = 0, 1
-RD_RX_NONE, RD_RX_ALLEN_CAHN, RD_RX_CAHN_HILLIARD, RD_RX_SCHNAKENBERG = 0, 1, 2, 3
+RD_OP_LAP5, RD_OP_BIHARM13, RD_OP_FCH6 = 0, 1, 2
+RD_RX_NONE, RD_RX_ALLEN_CAHN, RD_RX_CAHN_HILLIARD, RD_RX_SCHNAKENBERG, RD_RX_FCH = 0, 1, 2, 3, 4
 RD_FP64, RD_FP32_MIXED = 0, 1
 RD_INIT_PREV, RD_INIT_PROX = 0, 1
 
@@ -147,6 +147,7 @@ _KIND_TO_ABI = {
     "cahn_hilliard": (RD_OP_BIHARM13, RD_RX_CAHN_HILLIARD),
     "biharmonic": (RD_OP_BIHARM13, RD_RX_NONE),
     "schnakenberg": (RD_OP_LAP5, RD_RX_SCHNAKENBERG),
+    "fch": (RD_OP_FCH6, RD_RX_FCH),
 }
 
 

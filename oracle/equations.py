@@ -65,11 +65,17 @@ class Problem:
     a: float = 0.0
     sb: float = 0.0
     kappa: float = 1.0
+    dim: int = 2
     extra: dict = field(default_factory=dict)
 
     @property
     def h(self):
         return grid.spacing(self.N, self.L)
+
+    @property
+    def shape(self):
+        """Shape of one component's field."""
+        return (self.N,) * self.dim
 
     @property
     def ncomp(self):
@@ -115,13 +121,20 @@ def fch_w3(u):
     return 6.0 * u
 
 
+def _check_dim(prob):
+    if prob.dim == 3 and prob.kind not in (ALLEN_CAHN, HEAT, SCHNAKENBERG):
+        raise ValueError("3-D grids: 7-point Laplacian equations only (Allen-Cahn, heat, Schnakenberg)")
+
+
 def F(prob, U, Uk, ht):
-    """The step residual F(U); shape (N, N), or (2, N, N) for Schnakenberg."""
+    """The step residual F(U); shape prob.shape, or (2,) + prob.shape for Schnakenberg.
+    On 3-D grids the 5-point Laplacian is replaced by the 7-point one."""
+    _check_dim(prob)
     h, bc, k = prob.h, prob.bc, prob.kind
     if k == ALLEN_CAHN:
-        return U - Uk - ht * (prob.lam * grid.lap5(U, h, bc) + reaction_ac(U, prob.b))
+        return U - Uk - ht * (prob.lam * grid.lap(U, h, bc) + reaction_ac(U, prob.b))
     if k == HEAT:
-        return U - Uk - ht * prob.lam * grid.lap5(U, h, bc)
+        return U - Uk - ht * prob.lam * grid.lap(U, h, bc)
     if k == CAHN_HILLIARD:
         return (U - Uk + prob.lam * ht * grid.lap13(U, h, bc)
                 - ht * grid.lap5(chem_potential_ch(U, prob.b), h, bc))
@@ -136,19 +149,20 @@ def F(prob, U, Uk, ht):
         u, v = U[0], U[1]
         d1, d2 = prob.diff
         u2v = u * u * v
-        fu = u - Uk[0] - ht * (d1 * grid.lap5(u, h, bc) + prob.kappa * (prob.a - u + u2v))
-        fv = v - Uk[1] - ht * (d2 * grid.lap5(v, h, bc) + prob.kappa * (prob.sb - u2v))
+        fu = u - Uk[0] - ht * (d1 * grid.lap(u, h, bc) + prob.kappa * (prob.a - u + u2v))
+        fv = v - Uk[1] - ht * (d2 * grid.lap(v, h, bc) + prob.kappa * (prob.sb - u2v))
         return np.stack([fu, fv])
     raise ValueError(k)
 
 
 def adjoint(prob, U, Pt, ht):
     """grad F(U)^T P~, with the reaction derivative at the given (old) U."""
+    _check_dim(prob)
     h, bc, k = prob.h, prob.bc, prob.kind
     if k == ALLEN_CAHN:
-        return Pt - prob.lam * ht * grid.lap5(Pt, h, bc) - ht * reaction_ac_prime(U, prob.b) * Pt
+        return Pt - prob.lam * ht * grid.lap(Pt, h, bc) - ht * reaction_ac_prime(U, prob.b) * Pt
     if k == HEAT:
-        return Pt - prob.lam * ht * grid.lap5(Pt, h, bc)
+        return Pt - prob.lam * ht * grid.lap(Pt, h, bc)
     if k == CAHN_HILLIARD:
         return (Pt + prob.lam * ht * grid.lap13(Pt, h, bc)
                 - ht * chem_potential_ch_prime(U, prob.b) * grid.lap5(Pt, h, bc))
@@ -168,8 +182,8 @@ def adjoint(prob, U, Pt, ht):
         p, q = Pt[0], Pt[1]
         d1, d2 = prob.diff
         kap = prob.kappa
-        gu = p - ht * (d1 * grid.lap5(p, h, bc) + kap * (-p + 2.0 * u * v * (p - q)))
-        gv = q - ht * (d2 * grid.lap5(q, h, bc) + kap * u * u * (p - q))
+        gu = p - ht * (d1 * grid.lap(p, h, bc) + kap * (-p + 2.0 * u * v * (p - q)))
+        gv = q - ht * (d2 * grid.lap(q, h, bc) + kap * u * u * (p - q))
         return np.stack([gu, gv])
     raise ValueError(k)
 
@@ -209,9 +223,10 @@ def residual_norm(prob, W, ht):
 
 def jacobian(prob, U, ht):
     """Sparse Jacobian of F at U, assembled from the sparse Laplacian matrix."""
+    _check_dim(prob)
     N, h, bc, k = prob.N, prob.h, prob.bc, prob.kind
-    Lm = grid.lap5_matrix(N, h, bc)
-    I = sp.identity(N * N, format="csr")
+    Lm = grid.lap5_matrix(N, h, bc) if prob.dim == 2 else grid.lap7_matrix(N, h, bc)
+    I = sp.identity(N ** prob.dim, format="csr")
     if k == ALLEN_CAHN:
         return (I - ht * prob.lam * Lm - ht * sp.diags(reaction_ac_prime(U, prob.b).ravel())).tocsr()
     if k == HEAT:

@@ -1,6 +1,8 @@
-"""Discrete Laplacians on an N x N grid, FP64 (test infrastructure only).
+"""Discrete Laplacians on an N x N (or N x N x N) grid, FP64 (test infrastructure only).
 
-Fields are numpy arrays of shape (N, N) indexed ``[y, x]`` (x fastest).  Every
+Fields are numpy arrays of shape (N, N) indexed ``[y, x]`` (x fastest), or
+(N, N, N) indexed ``[z, y, x]`` for the 7-point Laplacian of 3-D grids (the
+paper poses the method on a domain in R^d; its examples are 2-D).  Every
 operator here is symmetric under x <-> y, so the paper's garbled vectorisation
 index (Sec. 2.1, just before eq. 11) does not change any result.
 
@@ -74,6 +76,20 @@ def lap13(u, h, bc):
     return (20.0 * at(0, 0) - 8.0 * axis1 + 2.0 * diag + axis2) / h4
 
 
+def lap7(u, h, bc):
+    """Seven-point Laplacian of a 3-D field: the 1-D second difference along each of
+    the three axes, with the same ghost rules as ``lap5``."""
+    e = _pad(np.asarray(u, dtype=np.float64), 1, bc)
+    c = e[1:-1, 1:-1, 1:-1]
+    return (e[1:-1, 1:-1, :-2] + e[1:-1, 1:-1, 2:] + e[1:-1, :-2, 1:-1] + e[1:-1, 2:, 1:-1]
+            + e[:-2, 1:-1, 1:-1] + e[2:, 1:-1, 1:-1] - 6.0 * c) / (h * h)
+
+
+def lap(u, h, bc):
+    """The Laplacian of a 2-D (5-point) or 3-D (7-point) field."""
+    return lap5(u, h, bc) if np.ndim(u) == 2 else lap7(u, h, bc)
+
+
 def _second_difference_1d(N, bc):
     """The N x N tridiagonal 1-D second difference (without 1/h^2).
 
@@ -110,6 +126,14 @@ def lap5_matrix(N, h, bc):
     T = _second_difference_1d(N, bc)
     I = sp.identity(N, format="csr")
     return ((sp.kron(I, T) + sp.kron(T, I)) / (h * h)).tocsr()
+
+
+def lap7_matrix(N, h, bc):
+    """Sparse N^3 x N^3 seven-point Laplacian, kron(I, I, T) + kron(I, T, I) + kron(T, I, I);
+    row index = (z * N + y) * N + x."""
+    T = _second_difference_1d(N, bc)
+    I = sp.identity(N, format="csr")
+    return ((sp.kron(I, sp.kron(I, T)) + sp.kron(I, sp.kron(T, I)) + sp.kron(T, sp.kron(I, I))) / (h * h)).tocsr()
 
 
 def apply_matrix(M, u):

@@ -39,22 +39,25 @@ def laplacian_eigenvalues_1d(N, h, bc):
     raise ValueError(bc)
 
 
-def laplacian_symbol(N, h, bc):
-    """2-D eigenvalues of ``-Lap``: mu[ky, kx] = s_ky + s_kx."""
+def laplacian_symbol(N, h, bc, dim=2):
+    """Eigenvalues of ``-Lap``: mu[ky, kx] = s_ky + s_kx (2-D), or
+    mu[kz, ky, kx] = s_kz + s_ky + s_kx for the 7-point Laplacian (3-D)."""
     s = laplacian_eigenvalues_1d(N, h, bc)
+    if dim == 3:
+        return s[:, None, None] + s[None, :, None] + s[None, None, :]
     return s[:, None] + s[None, :]
 
 
-def precond_symbol(N, h, bc, alpha, beta, gamma=0.0):
-    """Eigenvalues of ``G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2`` on the 2-D grid."""
-    mu = laplacian_symbol(N, h, bc)
+def precond_symbol(N, h, bc, alpha, beta, gamma=0.0, dim=2):
+    """Eigenvalues of ``G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2`` on the grid."""
+    mu = laplacian_symbol(N, h, bc, dim)
     return (1.0 + alpha * mu + beta * mu * mu + gamma * mu * mu * mu) ** 2
 
 
 def forward_transform(w, bc):
-    """2-D DFT (periodic) or orthonormal 2-D DCT-II (Neumann)."""
+    """DFT (periodic) or orthonormal DCT-II (Neumann) over every axis of the field."""
     if bc == grid.PERIODIC:
-        return np.fft.fft2(w)
+        return np.fft.fftn(w)
     if bc == grid.NEUMANN:
         return sfft.dctn(w, type=2, norm="ortho")
     raise ValueError(bc)
@@ -63,7 +66,7 @@ def forward_transform(w, bc):
 def inverse_transform(what, bc):
     """Inverse of ``forward_transform`` (real part for the periodic case)."""
     if bc == grid.PERIODIC:
-        return np.real(np.fft.ifft2(what))
+        return np.real(np.fft.ifftn(what))
     if bc == grid.NEUMANN:
         return sfft.idctn(what, type=2, norm="ortho")
     raise ValueError(bc)
@@ -75,7 +78,7 @@ def precond_solve(w, h, bc, alpha, beta, gamma=0.0):
     This is the step "Solve G Y_n = W_n via 2D FFT (DCT)" of Algorithm 1.
     """
     N = w.shape[0]
-    g = precond_symbol(N, h, bc, alpha, beta, gamma)
+    g = precond_symbol(N, h, bc, alpha, beta, gamma, dim=np.ndim(w))
     return inverse_transform(forward_transform(w, bc) / g, bc)
 
 

@@ -32,14 +32,19 @@ CONFIGS = {
                        a=0.1, sb=0.9, kappa=1.0, ht=1e-3, steps=100,
                        init=("steady_plus_uniform", -0.01, 0.01), seed=3,
                        tol=1e-4, tau=0.9, omega=1.0),
+    # 3-D grids with the 7-point Laplacian (the method is posed in R^d; the paper's
+    # examples are 2-D): Allen-Cahn on the unit cube, 128^3 points.
+    "ac3d128": dict(kind="allen_cahn", dim=3, N=128, L=1.0, bc=PERIODIC, diff=(0.01 ** 2,), b=1.0,
+                    ht=1e-3, steps=50, init=("uniform", -0.1, 0.1), seed=4,
+                    tol=1e-6, tau=0.9, omega=1.0),
 }
 
 SERVING_SIZES = (64, 128, 256, 512, 1024)
 
 
-def uniform_field(N, lo, hi, seed):
+def uniform_field(N, lo, hi, seed, dim=2):
     rng = np.random.default_rng(seed)
-    return rng.uniform(lo, hi, (N, N))
+    return rng.uniform(lo, hi, (N,) * dim)
 
 
 def initial_field(cfg, N=None, seed=None):
@@ -47,13 +52,14 @@ def initial_field(cfg, N=None, seed=None):
     N = cfg["N"] if N is None else N
     seed = cfg["seed"] if seed is None else seed
     kind, lo, hi = cfg["init"]
+    shape = (N,) * cfg.get("dim", 2)
     if kind == "uniform":
-        return uniform_field(N, lo, hi, seed)
+        return uniform_field(N, lo, hi, seed, cfg.get("dim", 2))
     if kind == "steady_plus_uniform":
         rng = np.random.default_rng(seed)
         a, b = cfg["a"], cfg["sb"]
-        u = (a + b) + rng.uniform(lo, hi, (N, N))
-        v = b / (a + b) ** 2 + rng.uniform(lo, hi, (N, N))
+        u = (a + b) + rng.uniform(lo, hi, shape)
+        v = b / (a + b) ** 2 + rng.uniform(lo, hi, shape)
         return np.stack([u, v])
     raise ValueError(kind)
 

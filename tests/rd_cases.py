@@ -9,7 +9,7 @@ from paper_2305_03945_amd import workloads as wl
 def oracle_problem(cfg, N=None, bc=None):
     return oeq.Problem(kind=cfg["kind"], N=N or cfg["N"], L=cfg.get("L", 1.0), bc=bc or cfg["bc"],
                        diff=tuple(cfg["diff"]), b=cfg.get("b", 1.0), a=cfg.get("a", 0.0), sb=cfg.get("sb", 0.0),
-                       kappa=cfg.get("kappa", 1.0))
+                       kappa=cfg.get("kappa", 1.0), dim=cfg.get("dim", 2))
 
 
 def oracle_opts(cfg, tol=None, max_iter=10000, init="prev"):

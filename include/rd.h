@@ -52,6 +52,7 @@ typedef enum {
 typedef enum { RD_BC_PERIODIC = 0, RD_BC_NEUMANN = 1 } rd_bc;
 
 /* Linear operator of F.  RD_OP_LAP5: +lambda Lap with the 5-point Laplacian (Sec. 2.1;
+ * on a 3-D grid the 7-point Laplacian;
  * periodic block-circulant form, or the Neumann L_1/L_2 form of Remark 1, eq. 24).
  * RD_OP_BIHARM13: -lambda Lap Lap with the 13-point stencil (= 5-point squared; Sec. 3.2).
  * RD_OP_FCH6: the sixth-order functionalized Cahn-Hilliard operator of Sec. 3.3 (nested
@@ -80,7 +81,11 @@ typedef struct {
     int32_t bc;              /* rd_bc                                                       */
     int32_t op;              /* rd_operator                                                 */
     int32_t rx;              /* rd_reaction_kind                                            */
-    int32_t pad0;
+    int32_t nz;              /* 0 or 1: 2-D grid.  nz = nx: 3-D cube of nx^3 points, layout
+                                [c][z][y][x], 7-point Laplacian (RD_OP_LAP5 equations only),
+                                16 <= nx <= 256; rd_step, rd_advance, rd_precond_solve and
+                                serving take it, the other kernel-level calls return
+                                RD_E_INVALID (the method is posed in R^d, Sec. 2)            */
     double diff[2];          /* lambda (diff[0]) or (D1, D2) for two components            */
     double p[4];             /* reaction parameters, see rd_reaction_kind                   */
 } rd_problem;

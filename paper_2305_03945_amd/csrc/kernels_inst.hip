@@ -1,6 +1,7 @@
 // Instantiates every FFT-carrying kernel for one grid size N = 2^RD_LOGN (set by
 // the build) and registers the launchers.
 #include "kernels.h"
+#include "kernels3d.h"
 #include "registry.h"
 
 #include <hip/hip_ext.h>
@@ -115,6 +116,81 @@ template <int BC, int EQ> void fill_mixed() {
     m.rows_per_block = row_block<float, EQ>();
 }
 
+// ---------------------------------------------------------------- 3-D launchers
+template <typename T, int BC, int EQ, int KIND>
+void launch3_rowfwd_fin(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
+    constexpr int R = row_block<T, EQ>();
+    constexpr int N = 1 << L;
+    hipExtLaunchKernelGGL((k3_row_forward<T, L, BC, EQ, KIND>), dim3(N * (N / R), nslots), dim3(NT), 0, st,
+                          ev_start(ev), nullptr, 0, slots);
+    hipExtLaunchKernelGGL((k_finalize<KIND, ncomp<EQ>()>), dim3(1, nslots), dim3(NT), 0, st, nullptr, ev_stop(ev), 0,
+                          slots);
+}
+
+template <typename T, int BC, int EQ, int PASS>
+void launch3_lines(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
+    constexpr int N = 1 << L;
+    constexpr int CB = line_cb<T, L>();
+    static_assert((N / 2) % CB == 0, "line blocks must tile the slots");
+    hipExtLaunchKernelGGL((k3_lines<T, L, BC, ncomp<EQ>(), PASS>), dim3(ncomp<EQ>() * N * ((N / 2) / CB), nslots),
+                          dim3(line_threads<T, L>()), 0, st, ev_start(ev), ev_stop(ev), 0, slots);
+}
+
+template <typename T, int BC, int EQ>
+void launch3_rowinv(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
+    constexpr int R = row_block<T, EQ>();
+    constexpr int N = 1 << L;
+    hipExtLaunchKernelGGL((k3_rowinv<T, L, BC, ncomp<EQ>()>), dim3(N * (N / R), nslots), dim3(NT), 0, st,
+                          ev_start(ev), ev_stop(ev), 0, slots);
+}
+
+template <typename T, int BC, int EQ, int MODE>
+void launch3_upd(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
+    constexpr size_t N = (size_t)1 << L;
+    constexpr int blocks = (int)((N * N * N / 4 + NT - 1) / NT);
+    hipExtLaunchKernelGGL((k3_upd<T, L, BC, EQ, MODE>), dim3(blocks, nslots), dim3(NT), 0, st, ev_start(ev),
+                          ev_stop(ev), 0, slots);
+}
+
+template <typename T, int BC, int EQ>
+void launch3_tin(Slot *const *slots, int nslots, const double *in, double *, hipStream_t st) {
+    constexpr int R = row_block<T, EQ>();
+    constexpr int N = 1 << L;
+    hipLaunchKernelGGL((k3_rows_transform_in<T, L, BC, ncomp<EQ>()>), dim3(N * (N / R), nslots), dim3(NT), 0, st,
+                       slots, in);
+}
+
+template <typename T, int BC, int EQ>
+void launch3_tout(Slot *const *slots, int nslots, const double *, double *out, hipStream_t st) {
+    constexpr int R = row_block<T, EQ>();
+    constexpr int N = 1 << L;
+    hipLaunchKernelGGL((k3_rows_transform_out<T, L, BC, ncomp<EQ>()>), dim3(N * (N / R), nslots), dim3(NT), 0, st,
+                       slots, out);
+}
+
+template <typename T, int BC, int EQ, int MODE> void fill3_mode(KSet &k) {
+    constexpr bool f64 = MODE == MODE_F64;
+    k.init = launch3_rowfwd_fin<T, BC, EQ, f64 ? K_INIT64 : K_OUTER_INIT>;
+    k.rowfwd = launch3_rowfwd_fin<T, BC, EQ, f64 ? K_ITER64 : K_INNER32>;
+    if constexpr (!f64) k.outer = launch3_rowfwd_fin<T, BC, EQ, K_OUTER_UPD>;
+    k.yfwd = launch3_lines<T, BC, EQ, L3_YFWD>;
+    k.zsym = launch3_lines<T, BC, EQ, L3_ZSYM>;
+    k.yinv = launch3_lines<T, BC, EQ, L3_YINV>;
+    k.rowinv = launch3_rowinv<T, BC, EQ>;
+    k.upd = launch3_upd<T, BC, EQ, MODE>;
+    k.tin = launch3_tin<T, BC, EQ>;
+    k.tout = launch3_tout<T, BC, EQ>;
+    k.rows_per_block = row_block<T, EQ>();
+    k.dim = 3;
+}
+
+template <int BC, int EQ> void fill3() {
+    if constexpr (L <= LOGN3_MAX) {
+        fill3_mode<double, BC, EQ, MODE_F64>(g_kernels3[MODE_F64][L][BC][EQ]);
+        fill3_mode<float, BC, EQ, MODE_MIXED>(g_kernels3[MODE_MIXED][L][BC][EQ]);
+    }
+}
+
 }  // namespace
 
 #define RD_CAT2(a, b) a##b
@@ -128,6 +204,10 @@ void RD_CAT(register_logn_, RD_LOGN)() {
     fill<BC_N, EQ_SCHNAK>();
     fill<BC_P, EQ_FCH>();
     fill<BC_N, EQ_FCH>();
+    fill3<BC_P, EQ_LAP5>();
+    fill3<BC_P, EQ_SCHNAK>();
+    fill3<BC_N, EQ_LAP5>();
+    fill3<BC_N, EQ_SCHNAK>();
 }
 
 }  // namespace rdk

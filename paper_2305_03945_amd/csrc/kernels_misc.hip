@@ -6,6 +6,7 @@
 namespace rdk {
 
 KSet g_kernels[2][LOGN_MAX + 1][2][EQ_COUNT];
+KSet g_kernels3[2][LOGN3_MAX + 1][2][EQ_COUNT];
 
 void launch_residual(int bc, int eq, const Slot *slot_dev, int N, const double *U, const double *Uk, double *W,
                      double *partials, hipStream_t st) {

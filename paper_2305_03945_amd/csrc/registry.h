@@ -21,13 +21,19 @@ struct KSet {
     launch_fn upd = nullptr;        // primal update (T)
     launch_fn rowfwd = nullptr;     // FP64: K_ITER64; mixed: K_INNER32 (no decision)
     launch_fn outer = nullptr;      // mixed: K_OUTER_UPD
+    launch_fn yfwd = nullptr;       // 3-D: forward y-transforms
+    launch_fn zsym = nullptr;       // 3-D: forward z-transform, symbol, inverse z-transform
+    launch_fn yinv = nullptr;       // 3-D: inverse y-transforms
     launch_io_fn tin = nullptr;     // precond-only: FP64 W -> row transforms into S
     launch_io_fn tout = nullptr;    // precond-only: S -> inverse rows -> FP64 Y
     int rows_per_block = 0;
+    int dim = 2;                    // 3: the 3-D launch sequence (row passes carry the decision)
 };
 
 constexpr int LOGN_MIN = 4, LOGN_MAX = 12;
+constexpr int LOGN3_MAX = 8;   // 3-D grids: N <= 256
 extern KSet g_kernels[2][LOGN_MAX + 1][2][EQ_COUNT];
+extern KSet g_kernels3[2][LOGN3_MAX + 1][2][EQ_COUNT];
 
 void register_upd_kernels();
 #define RD_DECLARE_LOGN(L) void register_logn_##L();

@@ -49,6 +49,9 @@ void register_all() {
 // ---------------------------------------------------------------- problem description
 struct Desc {
     int N = 0, logN = 0, C = 1, bc = 0, eq = 0, mode = 0;
+    int dim = 2;          // 2: N x N grid; 3: N x N x N grid (7-point Laplacian)
+    size_t pts = 0;       // points per component, N^dim
+    int rows = 0;         // x-rows per component, N^(dim-1)
     double h = 0;
 };
 
@@ -69,6 +72,17 @@ rd_status describe(const rd_problem *p, Desc &d) {
     d.logN = l;
     d.bc = p->bc == RD_BC_PERIODIC ? BC_P : BC_N;
     d.h = p->lx / p->nx;
+    d.dim = 2;
+    if (p->nz > 1) {
+        // 3-D: a cube of N^3 points, 7-point Laplacian equations only
+        if (p->nz != p->nx || l > LOGN3_MAX) return RD_E_INVALID;
+        if (p->op != RD_OP_LAP5) return RD_E_INVALID;
+        d.dim = 3;
+    } else if (p->nz < 0) {
+        return RD_E_INVALID;
+    }
+    d.pts = (size_t)d.N * d.N * (d.dim == 3 ? d.N : 1);
+    d.rows = d.N * (d.dim == 3 ? d.N : 1);
     if (p->op == RD_OP_LAP5 && (p->rx == RD_RX_NONE || p->rx == RD_RX_ALLEN_CAHN)) {
         d.eq = EQ_LAP5;
         d.C = 1;
@@ -86,6 +100,10 @@ rd_status describe(const rd_problem *p, Desc &d) {
     }
     if (!(p->diff[0] >= 0.0) || (d.C == 2 && !(p->diff[1] >= 0.0))) return RD_E_INVALID;
     return RD_OK;
+}
+
+const KSet &kset(int mode, const Desc &d) {
+    return d.dim == 3 ? g_kernels3[mode][d.logN][d.bc][d.eq] : g_kernels[mode][d.logN][d.bc][d.eq];
 }
 
 rd_status check_opts(const rd_opts *o) {
@@ -107,7 +125,8 @@ struct Tables {
 
 // ---------------------------------------------------------------- workspace of one slot
 struct Workspace {
-    int N = 0, C = 0, mode = 0, logN = 0, nblk = 0;
+    int N = 0, C = 0, mode = 0, logN = 0, nblk = 0, dim = 2;
+    size_t pts = 0;
     size_t bytes = 0;
     std::vector<void *> allocs;
     Slot *slot_dev = nullptr;     // device copy of the slot
@@ -118,10 +137,13 @@ struct Workspace {
     int last_iters = 0, last_outer = 0, last_inner = 0;
 };
 
-size_t field_bytes(int N, int C, size_t elem) { return (size_t)C * N * N * elem; }
+// pts: points per component (N^2 or N^3)
+size_t field_bytes(size_t pts, int C, size_t elem) { return (size_t)C * pts * elem; }
 
-size_t workspace_bytes(int N, int C, int mode, int rows_per_block) {
-    const size_t nblk = rows_per_block > 0 ? (size_t)N / rows_per_block : (size_t)N / 2;
+// rows: x-rows per component (N or N^2)
+size_t workspace_bytes(size_t pts, int rows, int C, int mode, int rows_per_block) {
+    const size_t nblk = rows_per_block > 0 ? (size_t)rows / rows_per_block : (size_t)rows / 2;
+    const size_t N = pts;
     size_t b = 0;
     if (mode == MODE_F64) {
         b += 5 * field_bytes(N, C, 8);   // U[2], P, Pt, S
@@ -146,7 +168,7 @@ struct Traj;
 struct Ctx {
     int device = 0;
     std::map<std::tuple<int, int, uint64_t>, Tables> tables;  // (N, bc, bits of h)
-    std::map<std::tuple<int, int, int>, std::unique_ptr<Workspace>> step_ws;  // (N, C, mode)
+    std::map<std::tuple<int, int, int, int>, std::unique_ptr<Workspace>> step_ws;  // (N, C, mode, dim)
     // scratch for kernel-level entry points
     Slot *scratch_slot_dev = nullptr;
     Slot *scratch_slot_host = nullptr;
@@ -202,16 +224,20 @@ void free_workspace(Workspace *w) {
     w->st_host = nullptr;
 }
 
-rd_status make_workspace(int N, int logN, int C, int mode, int eq, int bc, std::unique_ptr<Workspace> &out) {
+rd_status make_workspace(const Desc &d, int mode, std::unique_ptr<Workspace> &out) {
     auto w = std::make_unique<Workspace>();
-    w->N = N;
+    const int C = d.C;
+    const size_t N = d.pts;   // the field sizes below are per point
+    w->N = d.N;
     w->C = C;
     w->mode = mode;
-    w->logN = logN;
-    const KSet &k = g_kernels[mode][logN][bc][eq];
+    w->logN = d.logN;
+    w->dim = d.dim;
+    w->pts = d.pts;
+    const KSet &k = kset(mode, d);
     if (!k.init) return RD_E_INVALID;
-    w->nblk = N / k.rows_per_block;
-    w->bytes = workspace_bytes(N, C, mode, k.rows_per_block);
+    w->nblk = d.rows / k.rows_per_block;
+    w->bytes = workspace_bytes(d.pts, d.rows, C, mode, k.rows_per_block);
     Slot &s = w->proto;
     std::memset(&s, 0, sizeof(Slot));
     rd_status r;
@@ -384,6 +410,21 @@ void bind_workspace(Slot &s, const Workspace &w, const Tables &t) {
 // k_finalize so that the host and the outer pass see a decided State.
 void enqueue_round(const KSet &k, int mode, Slot *const *slots, int nslots, int iters, int passes, hipStream_t st) {
     const int np = mode == MODE_F64 ? 1 : passes;
+    if (k.dim == 3) {
+        // 3-D: every row pass carries its own stop decision
+        for (int p = 0; p < np; ++p) {
+            for (int i = 0; i < iters; ++i) {
+                k.yfwd(slots, nslots, st, nullptr);
+                k.zsym(slots, nslots, st, nullptr);
+                k.yinv(slots, nslots, st, nullptr);
+                k.rowinv(slots, nslots, st, nullptr);
+                k.upd(slots, nslots, st, nullptr);
+                k.rowfwd(slots, nslots, st, nullptr);
+            }
+            if (mode == MODE_MIXED) k.outer(slots, nslots, st, nullptr);
+        }
+        return;
+    }
     for (int p = 0; p < np; ++p) {
         for (int i = 0; i < iters; ++i) {
             (i == 0 ? k.cols : k.cols_fin)(slots, nslots, st, nullptr);
@@ -413,7 +454,7 @@ const void *final_buffer(const Workspace &w, const State &s) {
 }
 
 rd_status get_step_workspace(Ctx *c, const Desc &d, int mode, Workspace *&out) {
-    auto key = std::make_tuple(d.N, d.C, mode);
+    auto key = std::make_tuple(d.N, d.C, mode, d.dim);
     auto it = c->step_ws.find(key);
     if (it != c->step_ws.end()) {
         // a workspace is reusable across equations of the same shape; the
@@ -422,7 +463,7 @@ rd_status get_step_workspace(Ctx *c, const Desc &d, int mode, Workspace *&out) {
         return RD_OK;
     }
     std::unique_ptr<Workspace> w;
-    rd_status r = make_workspace(d.N, d.logN, d.C, mode, d.eq, d.bc, w);
+    rd_status r = make_workspace(d, mode, w);
     if (r != RD_OK) return r;
     out = w.get();
     c->step_ws[key] = std::move(w);
@@ -552,10 +593,10 @@ size_t rd_footprint_bytes(const rd_problem *prob, const rd_opts *opts) {
     if (describe(prob, d) != RD_OK || check_opts(opts) != RD_OK) return 0;
     std::call_once(g_register_once, register_all);
     const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
-    if (!g_kernels[mode][d.logN][d.bc][d.eq].init) return 0;   // no such precision for the equation
-    const int rpb = g_kernels[mode][d.logN][d.bc][d.eq].rows_per_block;
+    if (!kset(mode, d).init) return 0;   // no such precision for the equation
+    const int rpb = kset(mode, d).rows_per_block;
     // resident trajectory state + the step workspace
-    return workspace_bytes(d.N, d.C, mode, rpb) + field_bytes(d.N, d.C, 8);
+    return workspace_bytes(d.pts, d.rows, d.C, mode, rpb) + field_bytes(d.pts, d.C, 8);
 }
 
 rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t, const double *u_n,
@@ -570,7 +611,7 @@ rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double
     RD_CHECK(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
     const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
-    const KSet &k = g_kernels[mode][d.logN][d.bc][d.eq];
+    const KSet &k = kset(mode, d);
     if (!k.init) return RD_E_INVALID;   // no such precision for the equation
     Tables *t = nullptr;
     if ((r = get_tables(c, d.N, d.bc, d.h, t)) != RD_OK) return r;
@@ -584,7 +625,7 @@ rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double
     RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
     if ((r = run_step(c, *w, k, st, opts->max_iter, opts->max_outer)) != RD_OK) return r;
     const State &sf = *w->st_host;
-    RD_CHECK(hipMemcpyAsync(u_np1, final_buffer(*w, sf), field_bytes(d.N, d.C, 8), hipMemcpyDeviceToDevice, st));
+    RD_CHECK(hipMemcpyAsync(u_np1, final_buffer(*w, sf), field_bytes(d.pts, d.C, 8), hipMemcpyDeviceToDevice, st));
     RD_CHECK(hipStreamSynchronize(st));
     info_from_state(sf, mode, info);
     return (rd_status)sf.status;
@@ -602,7 +643,8 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
     RD_CHECK(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
     const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
-    const KSet &k = g_kernels[mode][d.logN][d.bc][d.eq];
+    if (d.dim != 2) return RD_E_INVALID;   // the kernel timing covers the 2-D launch sequence
+    const KSet &k = kset(mode, d);
     if (!k.init) return RD_E_INVALID;   // no such precision for the equation
     Tables *t = nullptr;
     if ((r = get_tables(c, d.N, d.bc, d.h, t)) != RD_OK) return r;
@@ -706,7 +748,7 @@ rd_status rd_advance(void *ctx, const rd_problem *prob, const rd_opts *opts, con
     if ((r = check_opts(opts)) != RD_OK) return r;
     RD_CHECK(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
-    const size_t fb = field_bytes(d.N, d.C, 8);
+    const size_t fb = field_bytes(d.pts, d.C, 8);
     double *next = nullptr;
     if (hipMalloc((void **)&next, fb) != hipSuccess) return RD_E_NOMEM;
     std::memset(info, 0, sizeof(*info));
@@ -768,7 +810,7 @@ rd_status rd_residual(void *ctx, const rd_problem *prob, double h_t, const doubl
     Desc d;
     rd_status r = describe(prob, d);
     if (r != RD_OK) return r;
-    if (!(h_t > 0.0)) return RD_E_INVALID;
+    if (!(h_t > 0.0) || d.dim != 2) return RD_E_INVALID;   // kernel-level calls: 2-D grids
     RD_CHECK(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
     Slot &s = *c->scratch_slot_host;
@@ -814,7 +856,7 @@ rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_
     RD_CHECK(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
     const int mode = precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
-    const KSet &k = g_kernels[mode][d.logN][d.bc][d.eq];
+    const KSet &k = kset(mode, d);
     if (!k.tin) return RD_E_INVALID;   // no such precision for the equation
     Tables *t = nullptr;
     if ((r = get_tables(c, d.N, d.bc, d.h, t)) != RD_OK) return r;
@@ -827,7 +869,13 @@ rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_
     RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
     RD_CHECK(hipMemsetAsync(w->proto.st, 0, sizeof(State), st));   // done = 0: column pass active
     k.tin(w->slot_list_dev, 1, w_in, nullptr, st);
-    k.cols(w->slot_list_dev, 1, st, nullptr);
+    if (d.dim == 3) {
+        k.yfwd(w->slot_list_dev, 1, st, nullptr);
+        k.zsym(w->slot_list_dev, 1, st, nullptr);
+        k.yinv(w->slot_list_dev, 1, st, nullptr);
+    } else {
+        k.cols(w->slot_list_dev, 1, st, nullptr);
+    }
     k.tout(w->slot_list_dev, 1, nullptr, y, st);
     RD_CHECK(hipGetLastError());
     RD_CHECK(hipStreamSynchronize(st));
@@ -840,7 +888,7 @@ rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *c
     Desc d;
     rd_status r = describe(prob, d);
     if (r != RD_OK) return r;
-    if (!(h_t > 0.0)) return RD_E_INVALID;
+    if (!(h_t > 0.0) || d.dim != 2) return RD_E_INVALID;   // kernel-level calls: 2-D grids
     RD_CHECK(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
     Slot &s = *c->scratch_slot_host;
@@ -875,11 +923,11 @@ rd_status rd_traj_open(void *ctx, const rd_problem *prob, const rd_opts *opts, c
     t->opts = *opts;
     t->d = d;
     t->d.mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
-    if (!g_kernels[t->d.mode][d.logN][d.bc][d.eq].init) {   // no such precision for the equation
+    if (!kset(t->d.mode, t->d).init) {   // no such precision for the equation
         delete t;
         return RD_E_INVALID;
     }
-    const size_t fb = field_bytes(d.N, d.C, 8);
+    const size_t fb = field_bytes(d.pts, d.C, 8);
     if (hipMalloc((void **)&t->u, fb) != hipSuccess) {
         delete t;
         return RD_E_NOMEM;
@@ -924,9 +972,9 @@ namespace {
 //  4. Read back the states, retire finished steps: copy U^{k+1} to the resident
 //     state, record the ticket's info.
 struct GroupKey {
-    int mode, logN, bc, eq;
+    int mode, logN, bc, eq, dim;
     bool operator<(const GroupKey &o) const {
-        return std::tie(mode, logN, bc, eq) < std::tie(o.mode, o.logN, o.bc, o.eq);
+        return std::tie(mode, logN, bc, eq, dim) < std::tie(o.mode, o.logN, o.bc, o.eq, o.dim);
     }
 };
 
@@ -978,11 +1026,11 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
     // 1. admission, in arrival order, while the resident budget allows
     while (!c->admit_queue.empty()) {
         Traj *t = c->admit_queue.front();
-        const size_t need = workspace_bytes(t->d.N, t->d.C, t->d.mode,
-                                            g_kernels[t->d.mode][t->d.logN][t->d.bc][t->d.eq].rows_per_block);
+        const size_t need = workspace_bytes(t->d.pts, t->d.rows, t->d.C, t->d.mode,
+                                            kset(t->d.mode, t->d).rows_per_block);
         if (c->budget && c->resident + need > c->budget && c->resident > 0) break;
         std::unique_ptr<Workspace> w;
-        r = make_workspace(t->d.N, t->d.logN, t->d.C, t->d.mode, t->d.eq, t->d.bc, w);
+        r = make_workspace(t->d, t->d.mode, w);
         if (r == RD_E_NOMEM && c->resident > 0) break;
         if (r != RD_OK) return r;
         t->ws = std::move(w);
@@ -994,7 +1042,7 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
     std::map<GroupKey, std::vector<Traj *>> starting, running;
     for (Traj *t : c->trajs) {
         if (!t->ws) continue;
-        GroupKey key{t->d.mode, t->d.logN, t->d.bc, t->d.eq};
+        GroupKey key{t->d.mode, t->d.logN, t->d.bc, t->d.eq, t->d.dim};
         if (!t->running && !t->pending.empty()) {
             starting[key].push_back(t);
             running[key].push_back(t);
@@ -1010,7 +1058,7 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
         const GroupKey &key = kv.first;
         hipStream_t st = c->serve_streams[gi++ % SERVE_STREAMS];
         gstream[key] = st;
-        const KSet &k = g_kernels[key.mode][key.logN][key.bc][key.eq];
+        const KSet &k = kset(key.mode, kv.second.front()->d);
         auto si = starting.find(key);
         if (si != starting.end()) {
             for (Traj *t : si->second) {
@@ -1060,7 +1108,7 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
             const State &s = *w.st_host;
             const bool fin = w.mode == MODE_F64 ? s.done != 0 : s.outer_done != 0;
             if (!fin) continue;
-            RD_CHECK(hipMemcpyAsync(t->u, final_buffer(w, s), field_bytes(t->d.N, t->d.C, 8),
+            RD_CHECK(hipMemcpyAsync(t->u, final_buffer(w, s), field_bytes(t->d.pts, t->d.C, 8),
                                     hipMemcpyDeviceToDevice, st));
             Ticket &tk = c->tickets[t->running_ticket];
             info_from_state(s, w.mode, &tk.info);
@@ -1107,7 +1155,7 @@ rd_status rd_traj_read(void *traj, double *u_out, void *hip_stream) {
     Traj *t = (Traj *)traj;
     RD_CHECK(hipSetDevice(t->ctx->device));
     hipStream_t st = (hipStream_t)hip_stream;
-    RD_CHECK(hipMemcpyAsync(u_out, t->u, field_bytes(t->d.N, t->d.C, 8), hipMemcpyDeviceToDevice, st));
+    RD_CHECK(hipMemcpyAsync(u_out, t->u, field_bytes(t->d.pts, t->d.C, 8), hipMemcpyDeviceToDevice, st));
     RD_CHECK(hipStreamSynchronize(st));
     return RD_OK;
 }

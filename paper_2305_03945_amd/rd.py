@@ -36,7 +36,7 @@ EXPORTED = ("rd_create", "rd_destroy", "rd_default_opts", "rd_footprint_bytes", 
 
 class Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
-                ("bc", ctypes.c_int32), ("op", ctypes.c_int32), ("rx", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("bc", ctypes.c_int32), ("op", ctypes.c_int32), ("rx", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("diff", ctypes.c_double * 2), ("p", ctypes.c_double * 4)]
 
 
@@ -151,10 +151,11 @@ _KIND_TO_ABI = {
 }
 
 
-def make_problem(kind, N, L=1.0, bc="periodic", diff=(1.0,), b=1.0, a=0.0, sb=0.0, kappa=1.0):
+def make_problem(kind, N, L=1.0, bc="periodic", diff=(1.0,), b=1.0, a=0.0, sb=0.0, kappa=1.0, dim=2):
     op, rx = _KIND_TO_ABI[kind]
     p = Problem()
     p.nx = p.ny = int(N)
+    p.nz = int(N) if dim == 3 else 0
     p.lx = p.ly = float(L)
     p.bc = RD_BC_PERIODIC if bc == "periodic" else RD_BC_NEUMANN
     p.op, p.rx = op, rx
@@ -170,7 +171,7 @@ def make_problem(kind, N, L=1.0, bc="periodic", diff=(1.0,), b=1.0, a=0.0, sb=0.
 def problem_from_config(cfg, N=None, bc=None):
     return make_problem(cfg["kind"], N or cfg["N"], cfg.get("L", 1.0), bc or cfg["bc"], cfg["diff"],
                         b=cfg.get("b", 1.0), a=cfg.get("a", 0.0), sb=cfg.get("sb", 0.0),
-                        kappa=cfg.get("kappa", 1.0))
+                        kappa=cfg.get("kappa", 1.0), dim=cfg.get("dim", 2))
 
 
 def make_opts(tol=1e-10, max_iter=10000, tau_u=0.9, tau_p=0.9, omega=1.0, precision="fp64", init="prev",

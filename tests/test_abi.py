@@ -36,7 +36,7 @@ def test_library_exports_every_declared_function(rd):
 def test_struct_layout_matches_header(rd):
     """Compile the header with the host C compiler and compare sizes and offsets."""
     fields = {
-        "rd_problem": (rd.Problem, ["nx", "ny", "lx", "ly", "bc", "op", "rx", "pad0", "diff", "p"]),
+        "rd_problem": (rd.Problem, ["nx", "ny", "lx", "ly", "bc", "op", "rx", "nz", "diff", "p"]),
         "rd_opts": (rd.Opts, ["tol", "max_iter", "max_outer", "tau_u", "tau_p", "omega", "precision", "init",
                               "inner_rtol"]),
         "rd_info": (rd.Info, ["iters", "outer", "residual_l2", "residual0", "mass_drift", "status", "pad0"]),

@@ -33,8 +33,8 @@ HBM_PEAK_GBS = 8000.0
 #   upd    : read P~, read U_n (mixed: e_n and the FP32 copy of U), write U_{n+1}
 #   rowfwd : read U_{n+1} and U^k (mixed: e, U_b, r), write the spectrum
 BYTES_PER_POINT = {
-    "fp64": {"cols": 16, "rowinv": 32, "upd": 24, "rowfwd": 24},
-    "mixed": {"cols": 8, "rowinv": 16, "upd": 16, "rowfwd": 16},
+    "fp64": {"cols": 16, "rowinv": 32, "upd": 24, "rowfwd": 24, "yfwd": 16, "zsym": 16, "yinv": 16},
+    "mixed": {"cols": 8, "rowinv": 16, "upd": 16, "rowfwd": 16, "yfwd": 8, "zsym": 8, "yinv": 8},
 }
 
 
@@ -102,9 +102,9 @@ def run_precision(ctx, rd, torch, cfg, u0, prec, steps, warmup):
         a, b = b, a
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    N = cfg["N"]
+    pts = cfg["N"] ** cfg.get("dim", 2)
     return dict(
-        pt_iters_per_s=N * N * iters / wall, wall_s=wall, ms_per_step=1e3 * wall / steps,
+        pt_iters_per_s=pts * iters / wall, wall_s=wall, ms_per_step=1e3 * wall / steps,
         p50_ms=1e3 * percentile(lat, 50), p99_ms=1e3 * percentile(lat, 99),
         iters_total=iters, iters_per_step=iters / steps, outer_total=outer, status=statuses,
     ), first, a
@@ -221,6 +221,30 @@ def adaptive_leg(ctx, rd, torch, cfg, u0):
                 step_sizes=sorted(set(round(h, 12) for h, _, ok in trace if ok)))
 
 
+def grid3d_leg(ctx, rd, torch, wl, steps):
+    """The 128^3 Allen-Cahn workload (7-point Laplacian, 3-D FFT preconditioner),
+    both precisions, the workload's step count (or ``steps`` if smaller)."""
+    cfg = dict(wl.CONFIGS["ac3d128"])
+    u0 = torch.tensor(wl.initial_field(cfg), dtype=torch.float64, device="cuda")
+    n = min(steps, cfg["steps"])
+    out = dict(workload="allen_cahn_128^3_periodic", steps=n)
+    finals = {}
+    for prec in ("fp64", "mixed"):
+        out[prec], _, finals[prec] = run_precision(ctx, rd, torch, cfg, u0, prec, n, 2)
+    out["mixed_vs_fp64_final_maxabs"] = float((finals["mixed"] - finals["fp64"]).abs().max().item())
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["wall_s"] / out["mixed"]["wall_s"]
+    p = rd.problem_from_config(cfg)
+    pts = cfg["N"] ** 3
+    out["kernels"] = {}
+    for prec in ("fp64", "mixed"):
+        o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], precision=prec)
+        ms = ctx.profile_iteration(u0, cfg["ht"], p, o, reps=20)
+        out["kernels"][prec] = {k: dict(ms=t, bytes=BYTES_PER_POINT[prec][k] * pts,
+                                        gbs=BYTES_PER_POINT[prec][k] * pts / (t * 1e-3) / 1e9)
+                                for k, t in ms.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,6 +312,10 @@ def main():
     adaptive = adaptive_leg(ctx, rd, torch, cfg, u0)
     log("  %s" % json.dumps(adaptive))
 
+    log("3-D grid: 128^3 Allen-Cahn")
+    grid3d = grid3d_leg(ctx, rd, torch, wl, args.steps)
+    log("  %s" % json.dumps(grid3d))
+
     serving = None
     if not args.no_serve:
         log("serving stream: %d trajectories x %d steps" % (args.serve_traj, args.serve_steps))
@@ -316,7 +344,7 @@ def main():
         "mixed": mx, "fp64": f64,
         "speedup_mixed_vs_fp64": f64["wall_s"] / mx["wall_s"],
         "accuracy": accuracy, "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu, "serving": serving,
-        "adaptive": adaptive,
+        "adaptive": adaptive, "grid3d": grid3d,
     }
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -16,11 +16,13 @@
  * from U_0 = U^k, P_0 = 0, stopped when ||Res(U_n)||_2 <= tol with Res = F / h_t
  * (Sec. 2.1, "Stopping criterion"; for two components the component norms are
  * added, Sec. 3.4.1).  G = (I - alpha Lap + beta Lap^2)^2 is inverted by a 2-D FFT
- * (periodic grids) or a 2-D DCT-II (Neumann grids, Remark 1).
+ * (periodic grids) or a 2-D DCT-II (Neumann grids, Remark 1); on 3-D grids by the
+ * 3-D transforms.
  *
  * Conventions for every entry point:
  *   - Array arguments documented as DEVICE are device (HBM) pointers; HOST ones are
- *     host pointers.  Fields are FP64, layout [ncomp][N][N], row-major, x fastest.
+ *     host pointers.  Fields are FP64, layout [ncomp][N][N] ([ncomp][N][N][N] on a 3-D
+ *     grid), row-major, x fastest.
  *   - The caller owns every array it passes; the library owns its workspaces.
  *   - Functions return rd_status; nothing throws across the ABI.
  *   - A context is not thread-safe: one host thread per context.
@@ -83,9 +85,10 @@ typedef struct {
     int32_t rx;              /* rd_reaction_kind                                            */
     int32_t nz;              /* 0 or 1: 2-D grid.  nz = nx: 3-D cube of nx^3 points, layout
                                 [c][z][y][x], 7-point Laplacian (RD_OP_LAP5 equations only),
-                                16 <= nx <= 256; rd_step, rd_advance, rd_precond_solve and
-                                serving take it, the other kernel-level calls return
-                                RD_E_INVALID (the method is posed in R^d, Sec. 2)            */
+                                16 <= nx <= 256; rd_step, rd_advance, rd_precond_solve,
+                                rd_profile_iteration and serving take it; rd_residual and
+                                rd_prox return RD_E_INVALID (the method is posed in R^d,
+                                Sec. 2)                                                     */
     double diff[2];          /* lambda (diff[0]) or (D1, D2) for two components            */
     double p[4];             /* reaction parameters, see rd_reaction_kind                   */
 } rd_problem;
@@ -204,9 +207,12 @@ rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *c
  * `reps` iterations in the solver's launch order, back to back, each launch recording
  * a start and a stop HIP event in its own dispatch packets (the kernel's begin and end
  * on that stream), so each kernel runs in the cache state the real loop leaves.  ms_out
- * (HOST, 4 doubles) receives the mean duration per launch in milliseconds of: column
- * pass (with the stop decision of the preceding row pass), inverse row pass + dual
- * update, primal update, residual + forward row pass.  Synchronises.                   */
+ * (HOST, 4 doubles on a 2-D grid, 6 on a 3-D one) receives the mean duration per launch
+ * in milliseconds of, 2-D: column pass (with the stop decision of the preceding row
+ * pass), inverse row pass + dual update, primal update, residual + forward row pass;
+ * 3-D: forward y-line pass, z-line pass (forward, symbol, inverse), inverse y-line
+ * pass, inverse x-row pass + dual update, primal update, residual + forward x-row pass
+ * with its stop decision.  Synchronises.                                               */
 rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
                                const double *u_n, int32_t reps, void *hip_stream, double *ms_out);
 

@@ -643,7 +643,6 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
     RD_CHECK(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
     const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
-    if (d.dim != 2) return RD_E_INVALID;   // the kernel timing covers the 2-D launch sequence
     const KSet &k = kset(mode, d);
     if (!k.init) return RD_E_INVALID;   // no such precision for the equation
     Tables *t = nullptr;
@@ -659,11 +658,17 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
     s.tol = 0.0;
     RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
     k.init(w->slot_list_dev, 1, st, nullptr);
-    // One untimed iteration from the initial state, its row pass left undecided.
-    k.cols(w->slot_list_dev, 1, st, nullptr);
-    k.rowinv(w->slot_list_dev, 1, st, nullptr);
-    k.upd(w->slot_list_dev, 1, st, nullptr);
-    k.rowfwd(w->slot_list_dev, 1, st, nullptr);
+    // The solver's launch order of one iteration (2-D: the stop decision of a row pass
+    // is taken by the next column pass; 3-D: by the row pass's own finalize).
+    std::vector<launch_fn> fns;
+    if (d.dim == 3)
+        fns = {k.yfwd, k.zsym, k.yinv, k.rowinv, k.upd, k.rowfwd};
+    else
+        fns = {k.cols_fin, k.rowinv, k.upd, k.rowfwd};
+    const int nk = (int)fns.size();
+    // One untimed iteration from the initial state.
+    for (int kk = 0; kk < nk; ++kk)
+        ((kk == 0 && d.dim == 2) ? k.cols : fns[kk])(w->slot_list_dev, 1, st, nullptr);
     RD_CHECK(hipGetLastError());
     RD_CHECK(hipStreamSynchronize(st));
     // No stop rule may end the timed iterations: tolerance 0 and max_iter 2^30 are
@@ -682,18 +687,17 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
     // reps iterations in the solver's launch order, back to back; every launch's
     // dispatch packets record a start and a stop event (the kernel's own begin and
     // end), so each kernel is timed in the cache state the real loop leaves it.
-    launch_fn fns[4] = {k.cols_fin, k.rowinv, k.upd, k.rowfwd};
-    std::vector<hipEvent_t> ev(8 * (size_t)reps);
+    std::vector<hipEvent_t> ev(2 * (size_t)nk * reps);
     for (auto &e : ev) RD_CHECK(hipEventCreate(&e));
     for (int i = 0; i < reps; ++i)
-        for (int kk = 0; kk < 4; ++kk) fns[kk](w->slot_list_dev, 1, st, &ev[8 * i + 2 * kk]);
+        for (int kk = 0; kk < nk; ++kk) fns[kk](w->slot_list_dev, 1, st, &ev[2 * (nk * i + kk)]);
     RD_CHECK(hipGetLastError());
     RD_CHECK(hipStreamSynchronize(st));
-    for (int kk = 0; kk < 4; ++kk) {
+    for (int kk = 0; kk < nk; ++kk) {
         double tot = 0.0;
         for (int i = 0; i < reps; ++i) {
             float ms = 0.f;
-            RD_CHECK(hipEventElapsedTime(&ms, ev[8 * i + 2 * kk], ev[8 * i + 2 * kk + 1]));
+            RD_CHECK(hipEventElapsedTime(&ms, ev[2 * (nk * i + kk)], ev[2 * (nk * i + kk) + 1]));
             tot += ms;
         }
         ms_out[kk] = tot / reps;

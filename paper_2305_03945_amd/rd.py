@@ -263,10 +263,12 @@ class Context:
 
     def profile_iteration(self, u, ht, problem, opts, reps=20, stream=None):
         """Mean launch duration (ms) of each kernel of one iteration, HIP events on `stream`."""
-        out = (ctypes.c_double * 4)()
+        out = (ctypes.c_double * 6)()
         _check(_lib.rd_profile_iteration(self._h, ctypes.byref(problem), ctypes.byref(opts), float(ht), _dptr(u),
                                          int(reps), _stream_ptr(stream), out), "rd_profile_iteration")
-        return dict(zip(("cols", "rowinv", "upd", "rowfwd"), list(out)))
+        names = ("yfwd", "zsym", "yinv", "rowinv", "upd", "rowfwd") if problem.nz > 1 else \
+            ("cols", "rowinv", "upd", "rowfwd")
+        return dict(zip(names, list(out)))
 
     def advance(self, u, t_end, problem, opts, adapt, t0=0.0, trace_cap=4096, stream=None):
         """Advance u in place from t0 to t_end with the adaptive step-size rule.

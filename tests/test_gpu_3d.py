@@ -161,3 +161,13 @@ def test_3d_argument_rules(ctx, rd):
     assert rd.footprint_bytes(big, rd.make_opts()) == 0
     ch = rd.make_problem("cahn_hilliard", 16, dim=3)
     assert rd.footprint_bytes(ch, rd.make_opts()) == 0
+
+
+def test_3d_kernel_timing(ctx, rd):
+    cfg = cfg3("allen_cahn", 64, "periodic")
+    p = rd.problem_from_config(cfg)
+    u = dev(wl.initial_field(cfg))
+    for prec in ("fp64", "mixed"):
+        ms = ctx.profile_iteration(u, cfg["ht"], p, rd.make_opts(tol=cfg["tol"], precision=prec), reps=3)
+        assert list(ms) == ["yfwd", "zsym", "yinv", "rowinv", "upd", "rowfwd"]
+        assert all(0.0 < t < 100.0 for t in ms.values()), ms

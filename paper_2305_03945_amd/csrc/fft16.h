@@ -75,10 +75,9 @@ template <typename T, int LOGN> struct Tw16 {
 };
 
 template <typename T, int LOGN>
-__device__ __forceinline__ void load_tw16(Tw16<T, LOGN> &w, const cplx<T> *__restrict__ tw) {
+__device__ __forceinline__ void load_tw16(Tw16<T, LOGN> &w, const cplx<T> *__restrict__ tw, int t) {
     constexpr int N = 1 << LOGN;
     constexpr int TPF = N / 16;
-    const int t = threadIdx.x % TPF;
     const auto tg = gp(tw);
 #pragma unroll
     for (int q = 1; q < npasses16<LOGN>(); ++q) {
@@ -97,58 +96,74 @@ __device__ __forceinline__ void load_tw16(Tw16<T, LOGN> &w, const cplx<T> *__res
     }
 }
 
+template <typename T, int LOGN>
+__device__ __forceinline__ void load_tw16(Tw16<T, LOGN> &w, const cplx<T> *__restrict__ tw) {
+    load_tw16<T, LOGN>(w, tw, (int)(threadIdx.x % ((1 << LOGN) / 16)));
+}
+
 // One Stockham pass of radix R (NS = product of earlier radices).  Butterfly j
 // reads x[j + r N/R], twiddles input r by W_{NS R}^{r k} (k = j mod NS), applies
 // DFT_R, and writes output q to ((j - k) R + k) + q NS.  pw: the thread's
-// gathered powers for this pass (unused when NS = 1).
+// gathered powers for this pass (unused when NS = 1).  Thread t of a transform
+// runs butterflies j = t + b N/16, b < 16/R.
+//
+// pass_in: the reads, twiddles and butterflies of the thread (outputs in v).
 template <typename T, int LOGN, int R, int NS, int DIR>
-__device__ __forceinline__ void pass16(cplx<T> *x, int t, bool active, const cplx<T> (*pw)[4]) {
+__device__ __forceinline__ void pass_in(const cplx<T> *x, int t, const cplx<T> (*pw)[4], cplx<T> (*v)[R]) {
     constexpr int N = 1 << LOGN;
     constexpr int TPF = N / 16;      // threads per transform
     constexpr int NB = N / R;        // butterflies
     constexpr int BPT = 16 / R;      // butterflies per thread
-    cplx<T> v[BPT][R];
-    if (active) {
 #pragma unroll
-        for (int b = 0; b < BPT; ++b) {
-            const int j = t + b * TPF;
+    for (int b = 0; b < BPT; ++b) {
+        const int j = t + b * TPF;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = x[lds_pad(j + r * NB)];
-            if constexpr (NS > 1) {
-                cplx<T> p[4];
+        for (int r = 0; r < R; ++r) v[b][r] = x[lds_pad(j + r * NB)];
+        if constexpr (NS > 1) {
+            cplx<T> p[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if ((1 << e) < R) {
+                    p[e] = pw[b][e];
+                    if constexpr (DIR > 0) p[e].im = -p[e].im;
+                }
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cplx<T> w = {(T)1, (T)0};
+                bool first = true;
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    if ((1 << e) < R) {
-                        p[e] = pw[b][e];
-                        if constexpr (DIR > 0) p[e].im = -p[e].im;
+                    if (r & (1 << e)) {
+                        w = first ? p[e] : cmul(w, p[e]);
+                        first = false;
                     }
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    cplx<T> w = {(T)1, (T)0};
-                    bool first = true;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (r & (1 << e)) {
-                            w = first ? p[e] : cmul(w, p[e]);
-                            first = false;
-                        }
-                    v[b][r] = cmul(v[b][r], w);
-                }
+                v[b][r] = cmul(v[b][r], w);
             }
-            dftR<T, R, DIR>(v[b]);
         }
+        dftR<T, R, DIR>(v[b]);
     }
+}
+
+// pass_out: the Stockham writes of the thread's butterfly outputs.
+template <typename T, int LOGN, int R, int NS>
+__device__ __forceinline__ void pass_out(cplx<T> *x, int t, const cplx<T> (*v)[R]) {
+    constexpr int TPF = (1 << LOGN) / 16;
+#pragma unroll
+    for (int b = 0; b < 16 / R; ++b) {
+        const int j = t + b * TPF;
+        const int k = j & (NS - 1);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) x[lds_pad(base + q * NS)] = v[b][q];
+    }
+}
+
+template <typename T, int LOGN, int R, int NS, int DIR>
+__device__ __forceinline__ void pass16(cplx<T> *x, int t, bool active, const cplx<T> (*pw)[4]) {
+    cplx<T> v[16 / R][R];
+    if (active) pass_in<T, LOGN, R, NS, DIR>(x, t, pw, v);
     __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int b = 0; b < BPT; ++b) {
-            const int j = t + b * TPF;
-            const int k = j & (NS - 1);
-            const int base = (j - k) * R + k;
-#pragma unroll
-            for (int q = 0; q < R; ++q) x[lds_pad(base + q * NS)] = v[b][q];
-        }
-    }
+    if (active) pass_out<T, LOGN, R, NS>(x, t, v);
     __syncthreads();
 }
 
@@ -162,6 +177,51 @@ __device__ __forceinline__ void passes16(cplx<T> *x, int t, bool active, const T
         pass16<T, LOGN, R, (1 << DONE), DIR>(x, t, active, w.p[q > 0 ? q - 1 : 0]);
         passes16<T, LOGN, DIR, DONE + LOGR>(x, t, active, w);
     }
+}
+
+// ---- transforms whose first input and last output stay in registers
+//
+// Thread t of a transform holds its 16 values in "stride order": value r is
+// element t + r N/16.  That is what the first radix-16 pass reads (NS = 1,
+// butterfly j = t) and, for the last pass of radix RL (NS = N/RL, butterflies
+// j = t + b N/16 with k = j), output q of butterfly b lands at
+// t + (b + q 16/RL) N/16, again element t + r N/16 with r = b + q 16/RL.  So a
+// transform can start from values loaded straight from global memory and end
+// with values ready to be stored, with LDS used only between passes.
+
+// Radix of the last pass and the register index of its output (b, q).
+template <int LOGN> constexpr int last_radix() { return pass_radix<LOGN>(npasses16<LOGN>() - 1); }
+template <int LOGN> __host__ __device__ constexpr int last_slot(int b, int q) { return b + q * (16 / last_radix<LOGN>()); }
+
+// Middle passes q = 1 .. npasses - 2 (all radix 16), each ending with a barrier.
+template <typename T, int LOGN, int DIR, int Q>
+__device__ __forceinline__ void middle_passes(cplx<T> *x, int t, const Tw16<T, LOGN> &w) {
+    if constexpr (Q < npasses16<LOGN>() - 1) {
+        pass16<T, LOGN, 16, (1 << (4 * Q)), DIR>(x, t, true, w.p[Q - 1]);
+        middle_passes<T, LOGN, DIR, Q + 1>(x, t, w);
+    }
+}
+
+// Transform of one region x whose input v (stride order) is in registers; the
+// output is left in v (stride order).  Needs at least two passes.  Starts by
+// writing x (the caller makes sure no thread still reads it) and ends with the
+// last pass's reads of x (the caller places a barrier before x is rewritten).
+template <typename T, int LOGN, int DIR>
+__device__ __forceinline__ void fft16_regs(cplx<T> *x, int t, const Tw16<T, LOGN> &w, cplx<T> *v) {
+    static_assert(npasses16<LOGN>() >= 2, "register-ended transforms need two passes");
+    constexpr int NP = npasses16<LOGN>();
+    constexpr int RL = last_radix<LOGN>();
+    dft16<T, DIR>(v);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[lds_pad(16 * t + q)] = v[q];
+    __syncthreads();
+    middle_passes<T, LOGN, DIR, 1>(x, t, w);
+    cplx<T> o[16 / RL][RL];
+    pass_in<T, LOGN, RL, (1 << (4 * (NP - 1))), DIR>(x, t, w.p[NP - 2], o);
+#pragma unroll
+    for (int b = 0; b < 16 / RL; ++b)
+#pragma unroll
+        for (int q = 0; q < RL; ++q) v[last_slot<LOGN>(b, q)] = o[b][q];
 }
 
 // In-place transforms of NREG regions (region i at buf + i * lds_region<LOGN>(),

@@ -619,6 +619,77 @@ template <typename T> __device__ __forceinline__ void spec_store(cplx<T> *p, con
     }
 }
 
+// Periodic rows: the pair spectra of a block's rows go from LDS (after the
+// forward transform) straight to the tiles of S, and back.  Item (reg, l), reg
+// fastest, owns slot l of the two rows packed in region reg: the rows are
+// adjacent in a tile, so the two values are one 16-byte access (FP32) or two
+// adjacent ones (FP64), and consecutive items walk the tile contiguously.
+// Region reg holds component reg / (R/2), rows 2 (reg % (R/2)) and the next.
+template <typename T, int LOGN, int C, int R>
+__device__ __forceinline__ cplx<T> *slot_pair(cplx<T> *S, int reg, int y0, int l) {
+    return &S[spec_off<R>(reg / (R / 2), y0 + 2 * (reg % (R / 2)), l, 1 << LOGN)];
+}
+
+template <typename T, int LOGN, int C, int R, int NTH>
+__device__ __forceinline__ void rows_post_store(const cplx<T> *buf, cplx<T> *S, int y0) {
+    constexpr int N = 1 << LOGN, H = N / 2;
+    constexpr int NREG = C * R / 2;
+    constexpr int TOT = NREG * H;
+#pragma unroll
+    for (int i = 0; i < (TOT + NTH - 1) / NTH; ++i) {
+        const int it = threadIdx.x + i * NTH;
+        if (TOT % NTH != 0 && it >= TOT) break;
+        const int reg = it % NREG, l = it / NREG;
+        cplx<T> v[2];
+        if (l == 0) {
+            const cplx<T> z0 = buf[rix<LOGN>(reg, 0)], zh = buf[rix<LOGN>(reg, H)];
+            v[0] = {z0.re, zh.re};
+            v[1] = {z0.im, zh.im};
+        } else {
+            const cplx<T> zl = buf[rix<LOGN>(reg, l)], zn = buf[rix<LOGN>(reg, N - l)];
+            v[0] = {(zl.re + zn.re) * (T)0.5, (zl.im - zn.im) * (T)0.5};
+            v[1] = {(zl.im + zn.im) * (T)0.5, (zn.re - zl.re) * (T)0.5};
+        }
+        cplx<T> *p = slot_pair<T, LOGN, C, R>(S, reg, y0, l);
+        if constexpr (spec_vec<T>() == 2) {
+            spec_store<T>(p, v);
+        } else {
+            spec_store<T>(p, v);
+            spec_store<T>(p + 1, v + 1);
+        }
+    }
+}
+
+template <typename T, int LOGN, int C, int R, int NTH>
+__device__ __forceinline__ void rows_load_pre(cplx<T> *buf, const cplx<T> *S, int y0) {
+    constexpr int N = 1 << LOGN, H = N / 2;
+    constexpr int NREG = C * R / 2;
+    constexpr int TOT = NREG * H;
+#pragma unroll
+    for (int i = 0; i < (TOT + NTH - 1) / NTH; ++i) {
+        const int it = threadIdx.x + i * NTH;
+        if (TOT % NTH != 0 && it >= TOT) break;
+        const int reg = it % NREG, l = it / NREG;
+        const cplx<T> *p = slot_pair<T, LOGN, C, R>(const_cast<cplx<T> *>(S), reg, y0, l);
+        cplx<T> v[2];
+        if constexpr (spec_vec<T>() == 2) {
+            spec_load<T>(p, v);
+        } else {
+            spec_load<T>(p, v);
+            spec_load<T>(p + 1, v + 1);
+        }
+        const cplx<T> a = v[0], b = v[1];
+        if (l == 0) {
+            buf[rix<LOGN>(reg, 0)] = {a.re, b.re};   // Z_0 = A_0 + i B_0
+            buf[rix<LOGN>(reg, H)] = {a.im, b.im};   // Z_{N/2}
+        } else {
+            buf[rix<LOGN>(reg, l)] = {a.re - b.im, a.im + b.re};
+            buf[rix<LOGN>(reg, N - l)] = {a.re + b.im, b.re - a.im};
+        }
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- row pass, forward
 template <typename T, int LOGN, int BC, int EQ, int KIND>
 __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
@@ -656,10 +727,13 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
     __syncthreads();
     const cplx<T> *twd = (const cplx<T> *)s.twd;
     wg_fft16<T, LOGN, -1, NREG, NT>(buf, twr);
+    cplx<T> *S = (cplx<T> *)s.S;
+    if constexpr (BC == BC_P) {
+        rows_post_store<T, LOGN, C, R, NT>(buf, S, y0);
+    } else {
     rows_post_forward<T, LOGN, BC, NREG, NT>(buf, twd);
     // Tile store: this workgroup's R rows are one contiguous block per component;
     // every access of the block is issued before any completes.
-    cplx<T> *S = (cplx<T> *)s.S;
     {
         constexpr int SV = spec_vec<T>();
         constexpr int TOT = C * R * H / SV;
@@ -678,6 +752,7 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
                 spec_store<T>(&S[spec_off<R>(c, y0 + r0, kx, N)], v);
             }
         }
+    }
     }
     write_partials<C>(s, tile, acc, scratch);
 }
@@ -711,6 +786,75 @@ template <typename T, int LOGN, int C> constexpr int col_waves_per_eu() {
     return w < 1 ? 1 : w;
 }
 
+// Periodic column pass with the transforms ended in registers (fft16_regs): each
+// thread loads its 16 values of one column straight from S, and the forward
+// transform's last pass, the symbol and the inverse transform's first pass run
+// on the same registers, so LDS is touched only between passes.  Lanes are laid
+// out so that R*CB consecutive lanes read R consecutive rows of the CB columns
+// of the block, one contiguous run of the tile layout.  Column 0 of a component
+// (which couples bins l and N - l) takes the LDS path instead.  Used for FP64:
+// measured at N = 2048 it takes the column pass from 26 to 21 us, while the FP32
+// pass, whose 16-byte tile loads carry two values each, is faster through LDS.
+template <typename T, int LOGN, int C> constexpr bool cols_in_regs() {
+    constexpr int TPF = (1 << LOGN) / 16;
+    constexpr int R = rows_per_block<T, LOGN, C>();
+    return sizeof(T) == 8 && npasses16<LOGN>() >= 2 && TPF >= R && TPF % R == 0;
+}
+
+template <typename T, int LOGN, int C, int CB>
+__device__ __forceinline__ void cols_regs(SlotRef s, int c, int kx0, cplx<T> *S, cplx<T> *buf) {
+    constexpr int N = 1 << LOGN, H = N / 2, TPF = N / 16;
+    constexpr int R = rows_per_block<T, LOGN, C>();
+    typedef T v2_t __attribute__((ext_vector_type(2)));
+    const int idx = threadIdx.x;
+    const int team = (idx / R) % CB;
+    const int t = (idx / (R * CB)) * R + idx % R;
+    const int kx = kx0 + team;
+    cplx<T> *x = buf + team * lds_region<LOGN>();
+    // element t + r N/16 of the column sits r * (N/16) * (N/2) slots after element t
+    const int o0 = (int)spec_off<R>(c, t, kx, N);
+    constexpr int STRIDE = TPF * H;
+    cplx<T> v[16];
+    {
+        const auto Sg = gp((const v2_t *)S);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const v2_t a = Sg[o0 + r * STRIDE];
+            v[r] = {a[0], a[1]};
+        }
+    }
+    {
+        Tw16<T, LOGN> twr;
+        load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw, t);
+        fft16_regs<T, LOGN, -1>(x, t, twr, v);
+    }
+    {
+        const double al = s.alpha[c], be = s.beta[c], ga = s.gamma[c];
+        const double invN2 = 1.0 / ((double)N * (double)N);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const T m = (T)symbol_mult(s.eig, kx, t + r * TPF, al, be, ga, invN2);
+            v[r] = {v[r].re * m, v[r].im * m};
+        }
+    }
+    __syncthreads();   // the last forward pass has read x
+    // gather the twiddles again rather than keeping them live across the symbol
+    __asm__ volatile("" ::: "memory");
+    {
+        Tw16<T, LOGN> twr;
+        load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw, t);
+        fft16_regs<T, LOGN, +1>(x, t, twr, v);
+    }
+    const auto So = gp((v2_t *)S);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        v2_t a;
+        a[0] = v[r].re;
+        a[1] = v[r].im;
+        So[o0 + r * STRIDE] = a;
+    }
+}
+
 // FIN >= 0: the launch has one extra workgroup (the last) that takes the stop
 // decision of the preceding row pass of kind FIN, in parallel with the column
 // transforms.  The other workgroups test the State as it was before that
@@ -739,6 +883,12 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>()), (col_waves_per_eu<T, L
     const int c = blockIdx.x / (H / CB);
     const int kx0 = (blockIdx.x % (H / CB)) * CB;
     cplx<T> *S = (cplx<T> *)s.S;
+    if constexpr (BC == BC_P && cols_in_regs<T, LOGN, C>()) {
+        if (kx0 > 0) {
+            cols_regs<T, LOGN, C, CB>(s, c, kx0, S, buf);
+            return;
+        }
+    }
     // consecutive threads: rows of a tile, then columns, then tiles; every load of
     // the block is issued before any completes
     constexpr int SV = spec_vec<T>();
@@ -808,7 +958,34 @@ __global__ __launch_bounds__(NT) void k_rowinv(Slot *const *slots) {
     Tw16<T, LOGN> twr;
     load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
     const cplx<T> *S = (const cplx<T> *)s.S;
-    {
+    const auto P = gp((T *)s.P);
+    const auto Pt = gp((T *)s.Pt);
+    const bool first = sst.iters == 0;
+    // four consecutive points per thread; P_n is loaded before the transforms
+    // (when it fits in 64 registers) so that its latency hides behind them
+    constexpr int TOTP = C * R * N / 4;
+    constexpr int PIT = (TOTP + NT - 1) / NT;
+    constexpr bool PREF = PIT * (int)sizeof(T) <= 64;
+    vec4_t<T> Pn[PIT];
+    auto load_P = [&](int i) {
+        const int idx = threadIdx.x + i * NT;
+        const int x0 = (idx & (N / 4 - 1)) * 4, rest = idx >> (LOGN - 2);
+        const int r = rest % R, c = rest / R;
+        if (first) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Pn[i][k] = (T)0;
+        } else {
+            Pn[i] = load4<T>(P + (c * NN + (size_t)(y0 + r) * N + x0));
+        }
+    };
+    if constexpr (PREF) {
+#pragma unroll
+        for (int i = 0; i < PIT; ++i)
+            if (TOTP % NT == 0 || threadIdx.x + i * NT < TOTP) load_P(i);
+    }
+    if constexpr (BC == BC_P) {
+        rows_load_pre<T, LOGN, C, R, NT>(buf, S, y0);
+    } else {
         constexpr int SV = spec_vec<T>();
         constexpr int TOT = C * R * H / SV;
 #pragma unroll
@@ -826,36 +1003,28 @@ __global__ __launch_bounds__(NT) void k_rowinv(Slot *const *slots) {
                 }
             }
         }
+        __syncthreads();
+        const cplx<T> *twd = (const cplx<T> *)s.twd;
+        rows_pre_inverse<T, LOGN, BC, NREG, NT>(buf, twd);
     }
-    __syncthreads();
-    const cplx<T> *twd = (const cplx<T> *)s.twd;
-    rows_pre_inverse<T, LOGN, BC, NREG, NT>(buf, twd);
     wg_fft16<T, LOGN, +1, NREG, NT>(buf, twr);
-    const auto P = gp((T *)s.P);
-    const auto Pt = gp((T *)s.Pt);
     const T tp = (T)s.tau_p, om = (T)s.omega;
-    const bool first = sst.iters == 0;
-    // four consecutive points per thread: vector loads and stores of P and P~
-#pragma unroll 4
-    for (int idx = threadIdx.x; idx < C * R * N / 4; idx += NT) {
+#pragma unroll
+    for (int i = 0; i < PIT; ++i) {
+        const int idx = threadIdx.x + i * NT;
+        if (TOTP % NT != 0 && idx >= TOTP) break;
         const int x0 = (idx & (N / 4 - 1)) * 4, rest = idx >> (LOGN - 2);
         const int r = rest % R, c = rest / R;
         const size_t g = c * NN + (size_t)(y0 + r) * N + x0;
-        vec4_t<T> Pn;
-        if (first) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) Pn[k] = (T)0;
-        } else {
-            Pn = load4<T>(P + g);
-        }
+        if constexpr (!PREF) load_P(i);
         vec4_t<T> Pn1, Ptl;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int pos = (BC == BC_P) ? x0 + k : dct_pos(x0 + k, N);
             const cplx<T> zv = buf[rix<LOGN>(c * R / 2 + r / 2, pos)];
             const T Y = (r & 1) ? zv.im : zv.re;
-            Pn1[k] = Pn[k] + tp * Y;
-            Ptl[k] = Pn1[k] + om * (Pn1[k] - Pn[k]);
+            Pn1[k] = Pn[i][k] + tp * Y;
+            Ptl[k] = Pn1[k] + om * (Pn1[k] - Pn[i][k]);
         }
         store4<T>(P + g, Pn1);
         store4<T>(Pt + g, Ptl);

@@ -9,8 +9,8 @@
 //   k3_rowinv      inverse x-transforms of Y -> P_{n+1}, P~ (eqs. 21-22)
 //   k3_upd         U_{n+1} = U_n - tau_u grad F(U_n)^T P~ (eq. 23)
 //   k3_row_forward W = F(U_{n+1}) (or F~(e)), partial norms, forward x-transforms
-//   (k_finalize)   stop decision
-//   k3_lines YFWD  forward y-transforms of the x-spectra
+//   k3_lines YFWD  forward y-transforms of the x-spectra; one extra workgroup
+//                  takes the stop decision of the preceding row pass
 //   k3_lines ZSYM  forward z-transform, multiply by 1 / (N^3 g), inverse z-transform
 //   k3_lines YINV  inverse y-transforms
 // The x-transform packs two real rows into one complex FFT exactly as the 2-D row
@@ -519,24 +519,98 @@ __device__ __forceinline__ void lines_apply_symbol3(cplx<T> *buf, int c, int q, 
     __syncthreads();
 }
 
+// Periodic lines of slots j > 0 are plain complex sequences: the y passes are
+// bare transforms and the z pass multiplies by the symbol at (kx, ky, kz) =
+// (j, q, l).  Their transforms start from and end in registers (fft16_regs):
+// thread t of team g holds elements t + r N/16 of the line of slot j0 + g, and
+// CB consecutive lanes take the CB adjacent slots (one 128-byte run).  FP64 only,
+// as for the 2-D column pass (measured: no gain for FP32).
+template <typename T, int LOGN> constexpr bool lines_in_regs() {
+    return sizeof(T) == 8 && npasses16<LOGN>() >= 2 &&
+           line_threads<T, LOGN>() == line_cb<T, LOGN>() * ((1 << LOGN) / 16);
+}
+
+template <typename T, int LOGN, int PASS>
+__device__ __forceinline__ void lines_regs(SlotRef s, int c, int w, int j0, cplx<T> *S, cplx<T> *buf) {
+    constexpr int N = 1 << LOGN, TPF = N / 16;
+    constexpr int CB = line_cb<T, LOGN>();
+    typedef T v2_t __attribute__((ext_vector_type(2)));
+    const int team = threadIdx.x % CB, t = threadIdx.x / CB;
+    const int j = j0 + team;
+    cplx<T> *x = buf + team * lds_region<LOGN>();
+    // element p of the line: y lines of plane (c, w), or z lines of row w
+    auto off = [&](int p) -> int {
+        return PASS == L3_ZSYM ? (int)s3_off<LOGN>(c, p, w, j) : (int)s3_off<LOGN>(c, w, p, j);
+    };
+    cplx<T> v[16];
+    {
+        const auto Sg = gp((const v2_t *)S);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const v2_t a = Sg[off(t + r * TPF)];
+            v[r] = {a[0], a[1]};
+        }
+    }
+    Tw16<T, LOGN> twr;
+    load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw, t);
+    if constexpr (PASS == L3_ZSYM) {
+        fft16_regs<T, LOGN, -1>(x, t, twr, v);
+        const double invN3 = 1.0 / ((double)N * (double)N * (double)N);
+        const double al = s.alpha[c], be = s.beta[c], ga = s.gamma[c];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const T m = (T)symbol3(s.eig, j, w, t + r * TPF, al, be, ga, invN3);
+            v[r] = {v[r].re * m, v[r].im * m};
+        }
+        __syncthreads();   // the last forward pass has read x
+        fft16_regs<T, LOGN, +1>(x, t, twr, v);
+    } else {
+        fft16_regs<T, LOGN, PASS == L3_YFWD ? -1 : +1>(x, t, twr, v);
+    }
+    const auto So = gp((v2_t *)S);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        v2_t a;
+        a[0] = v[r].re;
+        a[1] = v[r].im;
+        So[off(t + r * TPF)] = a;
+    }
+}
+
 // Lines of CB adjacent slots.  YFWD / YINV: the lines along y of plane (c, z);
 // ZSYM: the lines along z of row q (the y-transformed index) of component c.
-template <typename T, int LOGN, int BC, int C, int PASS>
+// FIN >= 0 (forward y pass only): one extra workgroup, the last, takes the stop
+// decision of the preceding row pass of kind FIN, as in the 2-D column pass.
+template <typename T, int LOGN, int BC, int C, int PASS, int FIN>
 __global__ __launch_bounds__((line_threads<T, LOGN>())) void k3_lines(Slot *const *slots) {
     constexpr int N = 1 << LOGN, H = N / 2;
     constexpr int CB = line_cb<T, LOGN>();
     constexpr int NTH = line_threads<T, LOGN>();
+    static_assert(FIN == FIN_NONE || PASS == L3_YFWD, "only the forward y pass takes a decision");
     __shared__ cplx<T> buf[CB * lds_region<LOGN>()];
+    __shared__ double lanes[FIN == FIN_NONE ? 1 : 64 * 2 * C];
     SlotRef s = slot_of(slots);
     StateRef sst = state_of(s);
+    if constexpr (FIN != FIN_NONE) {
+        if (blockIdx.x == gridDim.x - 1) {
+            if (!skip_launch<FIN>(sst)) reduce_and_finalize<FIN, C, NTH>(s, lanes);
+            return;
+        }
+    }
     if (skip_launch<K_ITER64>(sst)) return;
     // blockIdx.x -> (component, plane or row, first slot); CB divides N/2
     const int grp = blockIdx.x % (H / CB), rest = blockIdx.x / (H / CB);
     const int w = rest % N, c = rest / N;
     const int j0 = grp * CB;
+    cplx<T> *S = (cplx<T> *)s.S;
+    if constexpr (BC == BC_P && lines_in_regs<T, LOGN>()) {
+        if (j0 > 0) {
+            lines_regs<T, LOGN, PASS>(s, c, w, j0, S, buf);
+            return;
+        }
+    }
     Tw16<T, LOGN> twr;
     load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
-    cplx<T> *S = (cplx<T> *)s.S;
     // element p of the line of slot j
     auto off = [&](int p, int j) -> size_t {
         return PASS == L3_ZSYM ? s3_off<LOGN>(c, p, w, j) : s3_off<LOGN>(c, w, p, j);

@@ -127,13 +127,23 @@ void launch3_rowfwd_fin(Slot *const *slots, int nslots, hipStream_t st, hipEvent
                           slots);
 }
 
-template <typename T, int BC, int EQ, int PASS>
+template <typename T, int BC, int EQ, int PASS, int FIN>
 void launch3_lines(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
     constexpr int N = 1 << L;
     constexpr int CB = line_cb<T, L>();
     static_assert((N / 2) % CB == 0, "line blocks must tile the slots");
-    hipExtLaunchKernelGGL((k3_lines<T, L, BC, ncomp<EQ>(), PASS>), dim3(ncomp<EQ>() * N * ((N / 2) / CB), nslots),
-                          dim3(line_threads<T, L>()), 0, st, ev_start(ev), ev_stop(ev), 0, slots);
+    constexpr int extra = FIN == FIN_NONE ? 0 : 1;
+    hipExtLaunchKernelGGL((k3_lines<T, L, BC, ncomp<EQ>(), PASS, FIN>),
+                          dim3(ncomp<EQ>() * N * ((N / 2) / CB) + extra, nslots), dim3(line_threads<T, L>()), 0, st,
+                          ev_start(ev), ev_stop(ev), 0, slots);
+}
+
+template <typename T, int BC, int EQ, int KIND>
+void launch3_rowfwd(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
+    constexpr int R = row_block<T, EQ>();
+    constexpr int N = 1 << L;
+    hipExtLaunchKernelGGL((k3_row_forward<T, L, BC, EQ, KIND>), dim3(N * (N / R), nslots), dim3(NT), 0, st,
+                          ev_start(ev), ev_stop(ev), 0, slots);
 }
 
 template <typename T, int BC, int EQ>
@@ -170,12 +180,15 @@ void launch3_tout(Slot *const *slots, int nslots, const double *, double *out, h
 
 template <typename T, int BC, int EQ, int MODE> void fill3_mode(KSet &k) {
     constexpr bool f64 = MODE == MODE_F64;
+    constexpr int KIT = f64 ? K_ITER64 : K_INNER32;
     k.init = launch3_rowfwd_fin<T, BC, EQ, f64 ? K_INIT64 : K_OUTER_INIT>;
-    k.rowfwd = launch3_rowfwd_fin<T, BC, EQ, f64 ? K_ITER64 : K_INNER32>;
+    k.rowfwd = launch3_rowfwd<T, BC, EQ, KIT>;
+    k.fin = launch_fin<KIT, EQ>;
     if constexpr (!f64) k.outer = launch3_rowfwd_fin<T, BC, EQ, K_OUTER_UPD>;
-    k.yfwd = launch3_lines<T, BC, EQ, L3_YFWD>;
-    k.zsym = launch3_lines<T, BC, EQ, L3_ZSYM>;
-    k.yinv = launch3_lines<T, BC, EQ, L3_YINV>;
+    k.yfwd = launch3_lines<T, BC, EQ, L3_YFWD, FIN_NONE>;
+    k.yfwd_fin = launch3_lines<T, BC, EQ, L3_YFWD, KIT>;
+    k.zsym = launch3_lines<T, BC, EQ, L3_ZSYM, FIN_NONE>;
+    k.yinv = launch3_lines<T, BC, EQ, L3_YINV, FIN_NONE>;
     k.rowinv = launch3_rowinv<T, BC, EQ>;
     k.upd = launch3_upd<T, BC, EQ, MODE>;
     k.tin = launch3_tin<T, BC, EQ>;

@@ -22,6 +22,7 @@ struct KSet {
     launch_fn rowfwd = nullptr;     // FP64: K_ITER64; mixed: K_INNER32 (no decision)
     launch_fn outer = nullptr;      // mixed: K_OUTER_UPD
     launch_fn yfwd = nullptr;       // 3-D: forward y-transforms
+    launch_fn yfwd_fin = nullptr;   // 3-D: the same, plus the stop decision of the preceding row pass
     launch_fn zsym = nullptr;       // 3-D: forward z-transform, symbol, inverse z-transform
     launch_fn yinv = nullptr;       // 3-D: inverse y-transforms
     launch_io_fn tin = nullptr;     // precond-only: FP64 W -> row transforms into S

@@ -411,16 +411,17 @@ void bind_workspace(Slot &s, const Workspace &w, const Tables &t) {
 void enqueue_round(const KSet &k, int mode, Slot *const *slots, int nslots, int iters, int passes, hipStream_t st) {
     const int np = mode == MODE_F64 ? 1 : passes;
     if (k.dim == 3) {
-        // 3-D: every row pass carries its own stop decision
+        // 3-D: the forward y pass takes the decision of the preceding row pass
         for (int p = 0; p < np; ++p) {
             for (int i = 0; i < iters; ++i) {
-                k.yfwd(slots, nslots, st, nullptr);
+                (i == 0 ? k.yfwd : k.yfwd_fin)(slots, nslots, st, nullptr);
                 k.zsym(slots, nslots, st, nullptr);
                 k.yinv(slots, nslots, st, nullptr);
                 k.rowinv(slots, nslots, st, nullptr);
                 k.upd(slots, nslots, st, nullptr);
                 k.rowfwd(slots, nslots, st, nullptr);
             }
+            k.fin(slots, nslots, st, nullptr);
             if (mode == MODE_MIXED) k.outer(slots, nslots, st, nullptr);
         }
         return;
@@ -658,17 +659,18 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
     s.tol = 0.0;
     RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
     k.init(w->slot_list_dev, 1, st, nullptr);
-    // The solver's launch order of one iteration (2-D: the stop decision of a row pass
-    // is taken by the next column pass; 3-D: by the row pass's own finalize).
+    // The solver's launch order of one iteration (the stop decision of a row pass is
+    // taken by the next column pass, 2-D, or forward y pass, 3-D).
     std::vector<launch_fn> fns;
     if (d.dim == 3)
-        fns = {k.yfwd, k.zsym, k.yinv, k.rowinv, k.upd, k.rowfwd};
+        fns = {k.yfwd_fin, k.zsym, k.yinv, k.rowinv, k.upd, k.rowfwd};
     else
         fns = {k.cols_fin, k.rowinv, k.upd, k.rowfwd};
     const int nk = (int)fns.size();
-    // One untimed iteration from the initial state.
+    // One untimed iteration from the initial state (whose decision the initial
+    // pass has taken).
     for (int kk = 0; kk < nk; ++kk)
-        ((kk == 0 && d.dim == 2) ? k.cols : fns[kk])(w->slot_list_dev, 1, st, nullptr);
+        (kk == 0 ? (d.dim == 3 ? k.yfwd : k.cols) : fns[kk])(w->slot_list_dev, 1, st, nullptr);
     RD_CHECK(hipGetLastError());
     RD_CHECK(hipStreamSynchronize(st));
     // No stop rule may end the timed iterations: tolerance 0 and max_iter 2^30 are

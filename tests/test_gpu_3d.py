@@ -44,7 +44,7 @@ BCS = ["periodic", "neumann"]
 
 @pytest.mark.parametrize("kind", ["allen_cahn", "schnakenberg"])
 @pytest.mark.parametrize("bc", BCS)
-@pytest.mark.parametrize("N", [16, 32, 64])
+@pytest.mark.parametrize("N", [16, 32, 64, 128])
 def test_precond_3d(ctx, rd, kind, bc, N):
     cfg = cfg3(kind, N, bc)
     op = oracle_problem(cfg)

@@ -73,6 +73,20 @@ def test_step_fp64_matches_oracle(ctx, rd, kind, bc, N):
 
 
 @pytest.mark.parametrize("kind", ["allen_cahn", "schnakenberg"])
+@pytest.mark.parametrize("N", [512, 1024])
+def test_step_periodic_large_columns(ctx, rd, kind, N):
+    """Periodic grids whose column transforms run from registers (N >= 512): one
+    step in FP64 (equal iterations, 1e-10) and in mixed precision (1e-5)."""
+    cfg = small_cfg(kind, N, "periodic")
+    tol = 1e-7 if kind == "allen_cahn" else 1e-5
+    U0 = wl.initial_field(cfg, N=N, seed=10)
+    U1 = compare_fp64(ctx, rd, cfg, U0, 1, tol=tol)
+    Ug, info = ctx.step(dev(U0), cfg["ht"], rd.problem_from_config(cfg), gpu_opts(rd, cfg, "mixed", tol=tol))
+    assert info["status"] == "ok" and info["residual"] <= tol
+    assert max_abs(Ug.cpu().numpy(), U1) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["allen_cahn", "schnakenberg"])
 def test_step_fp64_prox_init_matches_oracle(ctx, rd, kind):
     cfg = small_cfg(kind, 64, "periodic")
     tol = 1e-8 if kind == "allen_cahn" else 1e-7

@@ -222,7 +222,10 @@ __device__ __forceinline__ void cols_apply_symbol(cplx<T> *buf, int job0, int nj
     constexpr int N = 1 << LOGN, H = N / 2;
     constexpr int IPT = pair_items_per_thread<LOGN, NREG, NTH>();
     const double invN2 = 1.0 / ((double)N * (double)N);
-#pragma unroll
+    // FP32: not unrolled, which keeps the FP32 column pass within 128 registers
+    // (no spills) so that two of its workgroups fit on a compute unit
+    constexpr int UNR = sizeof(T) == 4 ? 1 : IPT;
+#pragma unroll UNR
     for (int i = 0; i < IPT; ++i) {
         const int it = threadIdx.x + i * NTH;
         if (it >= NREG * H) break;

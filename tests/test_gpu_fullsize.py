@@ -92,3 +92,39 @@ def test_ac2048_sampled_residual_after_steps(ctx, rd):
     U, Uk = u.cpu().numpy(), uk.cpu().numpy()
     W = oeq.F(op, U, Uk, cfg["ht"])
     assert np.sqrt(np.sum((W / cfg["ht"]) ** 2)) <= cfg["tol"] * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+def test_largest_grid_step_4096(ctx, rd, bc):
+    """The largest 2-D grid, one Allen-Cahn step in each precision: both stop at the
+    tolerance by the oracle's own F, and agree with each other to the mixed bar."""
+    cfg = small_cfg("allen_cahn", 4096, bc)
+    op = oracle_problem(cfg)
+    p = rd.problem_from_config(cfg)
+    U0 = wl.initial_field(cfg, N=4096, seed=11)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], precision=prec)
+        u, info = ctx.step(dev(U0), cfg["ht"], p, o)
+        assert info["status"] == "ok" and info["residual"] <= cfg["tol"], (prec, info)
+        out[prec] = u.cpu().numpy()
+        assert oeq.residual_norm(op, oeq.F(op, out[prec], U0, cfg["ht"]), cfg["ht"]) <= cfg["tol"] * (1 + 1e-6)
+    assert max_abs(out["fp64"], out["mixed"]) <= 1e-5
+
+
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+def test_largest_grid_step_3d_256(ctx, rd, bc):
+    """The largest 3-D grid (256^3), one Allen-Cahn step in each precision, checked the same way."""
+    cfg = dict(wl.CONFIGS["ac3d128"])
+    cfg.update(N=256, bc=bc)
+    op = oracle_problem(cfg)
+    p = rd.problem_from_config(cfg)
+    U0 = wl.initial_field(cfg, seed=12)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], precision=prec)
+        u, info = ctx.step(dev(U0), cfg["ht"], p, o)
+        assert info["status"] == "ok" and info["residual"] <= cfg["tol"], (prec, info)
+        out[prec] = u.cpu().numpy()
+        assert oeq.residual_norm(op, oeq.F(op, out[prec], U0, cfg["ht"]), cfg["ht"]) <= cfg["tol"] * (1 + 1e-6)
+    assert max_abs(out["fp64"], out["mixed"]) <= 1e-5

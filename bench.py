@@ -123,7 +123,37 @@ def cpu_oracle_sample(cfg, u0_np):
     return r, dict(value=N * N * r.iters / wall, unit="grid-point-iters/s", cores=max(1, round(cpu / wall)),
                    kind="oracle", wall_s=round(wall, 3),
                    sample="first implicit step of the %dx%d Allen-Cahn workload, %d PDHG iterations to the "
-                          "workload tolerance" % (N, N, r.iters))
+                          "workload tolerance" % (N, N, r.iters),
+                   host=host_info(), other=oracle_other())
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(cpu_model=model, nproc=os.cpu_count(), omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
+
+
+def oracle_other():
+    """The oracle on the first steps of the two smaller 2-D workloads (64^2 Allen-Cahn,
+    512^2 Cahn-Hilliard): grid-point-iters/s and per-step latency, a few seconds in all."""
+    from oracle import pdhg as opdhg
+    from paper_2305_03945_amd import workloads as wl
+    from tests.rd_cases import oracle_opts, oracle_problem
+    out = {}
+    for name in ("ac64", "ch512"):
+        cfg = wl.CONFIGS[name]
+        u = wl.initial_field(cfg)
+        t0 = time.perf_counter()
+        r = opdhg.step(oracle_problem(cfg), u, cfg["ht"], oracle_opts(cfg))
+        wall = time.perf_counter() - t0
+        out[name] = dict(pt_iters_per_s=cfg["N"] ** 2 * r.iters / wall, step_ms=1e3 * wall, iters=r.iters)
+    return out
 
 
 def serve_stream(ctx, rd, torch, reqs, rate):
@@ -221,6 +251,34 @@ def adaptive_leg(ctx, rd, torch, cfg, u0):
                 step_sizes=sorted(set(round(h, 12) for h, _, ok in trace if ok)))
 
 
+def kernel_table(ctx, rd, cfg, u0, prec, pts, reps=20):
+    p = rd.problem_from_config(cfg)
+    o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], precision=prec)
+    ms = ctx.profile_iteration(u0, cfg["ht"], p, o, reps=reps)
+    return {k: dict(ms=t, bytes=BYTES_PER_POINT[prec][k] * pts,
+                    gbs=BYTES_PER_POINT[prec][k] * pts / (t * 1e-3) / 1e9) for k, t in ms.items()}
+
+
+def hbm_leg(ctx, rd, torch, wl, steps):
+    """The 2048^2 Allen-Cahn parameters on 4096^2 (working set beyond the last-level
+    cache): both precisions, per-kernel durations and the whole-iteration HBM rate."""
+    cfg = dict(wl.CONFIGS["ac4096"])
+    u0 = torch.tensor(wl.initial_field(cfg), dtype=torch.float64, device="cuda")
+    n = min(steps, cfg["steps"])
+    out = dict(workload="allen_cahn_4096_periodic", steps=n)
+    pts = cfg["N"] ** 2
+    for prec in ("fp64", "mixed"):
+        out[prec], _, _ = run_precision(ctx, rd, torch, cfg, u0, prec, n, 1)
+        k = kernel_table(ctx, rd, cfg, u0, prec, pts)
+        it_ms = sum(v["ms"] for v in k.values())
+        it_bytes = sum(v["bytes"] for v in k.values())
+        out[prec]["kernels"] = k
+        out[prec]["iteration_gbs"] = it_bytes / (it_ms * 1e-3) / 1e9
+    del u0
+    torch.cuda.empty_cache()
+    return out
+
+
 def grid3d_leg(ctx, rd, torch, wl, steps):
     """The 128^3 Allen-Cahn workload (7-point Laplacian, 3-D FFT preconditioner),
     both precisions, the workload's step count (or ``steps`` if smaller)."""
@@ -233,15 +291,7 @@ def grid3d_leg(ctx, rd, torch, wl, steps):
         out[prec], _, finals[prec] = run_precision(ctx, rd, torch, cfg, u0, prec, n, 2)
     out["mixed_vs_fp64_final_maxabs"] = float((finals["mixed"] - finals["fp64"]).abs().max().item())
     out["speedup_mixed_vs_fp64"] = out["fp64"]["wall_s"] / out["mixed"]["wall_s"]
-    p = rd.problem_from_config(cfg)
-    pts = cfg["N"] ** 3
-    out["kernels"] = {}
-    for prec in ("fp64", "mixed"):
-        o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], precision=prec)
-        ms = ctx.profile_iteration(u0, cfg["ht"], p, o, reps=20)
-        out["kernels"][prec] = {k: dict(ms=t, bytes=BYTES_PER_POINT[prec][k] * pts,
-                                        gbs=BYTES_PER_POINT[prec][k] * pts / (t * 1e-3) / 1e9)
-                                for k, t in ms.items()}
+    out["kernels"] = {prec: kernel_table(ctx, rd, cfg, u0, prec, cfg["N"] ** 3) for prec in ("fp64", "mixed")}
     return out
 
 
@@ -312,6 +362,10 @@ def main():
     adaptive = adaptive_leg(ctx, rd, torch, cfg, u0)
     log("  %s" % json.dumps(adaptive))
 
+    log("4096^2 Allen-Cahn (working set beyond the last-level cache)")
+    hbm4096 = hbm_leg(ctx, rd, torch, wl, args.steps)
+    log("  %s" % json.dumps({p: hbm4096[p]["pt_iters_per_s"] for p in ("fp64", "mixed")}))
+
     log("3-D grid: 128^3 Allen-Cahn")
     grid3d = grid3d_leg(ctx, rd, torch, wl, args.steps)
     log("  %s" % json.dumps(grid3d))
@@ -344,7 +398,7 @@ def main():
         "mixed": mx, "fp64": f64,
         "speedup_mixed_vs_fp64": f64["wall_s"] / mx["wall_s"],
         "accuracy": accuracy, "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu, "serving": serving,
-        "adaptive": adaptive, "grid3d": grid3d,
+        "adaptive": adaptive, "grid3d": grid3d, "hbm4096": hbm4096,
     }
     ctx.close()
     print(json.dumps(line), flush=True)

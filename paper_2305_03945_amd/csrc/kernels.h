@@ -761,7 +761,7 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
 // A workgroup takes CB adjacent columns of one component, one transform per
 // N/16 threads.  CB is chosen so that the CB x R block of a spectrum tile it
 // reads is at least 128 bytes (and the workgroup at least one wave), as far as
-// 96 KB of LDS and 1024 threads allow.
+// 156 KB of LDS (of the 160 KB a gfx950 workgroup may hold) and 1024 threads allow.
 template <typename T, int LOGN, int C> constexpr int col_jobs() {
     constexpr int N = 1 << LOGN;
     constexpr int R = rows_per_block<T, LOGN, C>();
@@ -769,8 +769,9 @@ template <typename T, int LOGN, int C> constexpr int col_jobs() {
     constexpr int by_tile = tile_bytes >= 128 ? 1 : 128 / tile_bytes;
     constexpr int by_wave = (N / 16 >= 64) ? 1 : 64 / (N / 16);
     constexpr int want = by_tile > by_wave ? by_tile : by_wave;
-    // LDS (<= 96 KB) and threads (<= 1024) bound it from above
-    constexpr int by_lds = 98304 / (lds_region<LOGN>() * (int)sizeof(cplx<T>));
+    // LDS (<= 156 KB, leaving room for the decision lanes) and threads (<= 1024)
+    // bound it from above
+    constexpr int by_lds = 159744 / (lds_region<LOGN>() * (int)sizeof(cplx<T>));
     constexpr int by_thr = 1024 / (N / 16 >= 1 ? N / 16 : 1);
     constexpr int cap = by_lds < by_thr ? by_lds : by_thr;
     constexpr int cb0 = want < cap ? want : cap;
@@ -780,9 +781,12 @@ template <typename T, int LOGN, int C> constexpr int col_jobs() {
 }
 template <typename T, int LOGN, int C> constexpr int col_threads() { return col_jobs<T, LOGN, C>() * ((1 << LOGN) / 16); }
 // Register budget: two column workgroups must fit on one CU (four SIMDs), so that
-// the extra decision workgroup of a launch that fills every CU starts at once.
+// the extra decision workgroup of a launch that fills every CU starts at once --
+// where their LDS fits twice in the CU's 160 KB; otherwise one.
 template <typename T, int LOGN, int C> constexpr int col_waves_per_eu() {
-    constexpr int w = 2 * col_threads<T, LOGN, C>() / 64 / 4;
+    constexpr int lds = col_jobs<T, LOGN, C>() * lds_region<LOGN>() * (int)sizeof(cplx<T>);
+    constexpr int per_cu = 2 * lds + 4096 <= 163840 ? 2 : 1;
+    constexpr int w = per_cu * col_threads<T, LOGN, C>() / 64 / 4;
     return w < 1 ? 1 : w;
 }
 

@@ -32,6 +32,11 @@ CONFIGS = {
                        a=0.1, sb=0.9, kappa=1.0, ht=1e-3, steps=100,
                        init=("steady_plus_uniform", -0.01, 0.01), seed=3,
                        tol=1e-4, tau=0.9, omega=1.0),
+    # The 2048^2 Allen-Cahn parameters on a 4096^2 grid: a working set (about 0.8 GB)
+    # beyond the 256 MB last-level cache, measured only.
+    "ac4096": dict(kind="allen_cahn", N=4096, L=1.0, bc=PERIODIC, diff=(0.01 ** 2,), b=1.0,
+                   ht=1e-3, steps=20, init=("uniform", -0.1, 0.1), seed=6,
+                   tol=1e-6, tau=0.9, omega=1.0),
     # 3-D grids with the 7-point Laplacian (the method is posed in R^d; the paper's
     # examples are 2-D): Allen-Cahn on the unit cube, 128^3 points.
     "ac3d128": dict(kind="allen_cahn", dim=3, N=128, L=1.0, bc=PERIODIC, diff=(0.01 ** 2,), b=1.0,

@@ -279,6 +279,52 @@ def hbm_leg(ctx, rd, torch, wl, steps):
     return out
 
 
+def paper_examples_leg(ctx, rd, torch, wl, steps):
+    """The paper's examples at their own sizes (128^2) and parameters: the sixth-order
+    FCH equation (Sec. 3.3, FP64), Schnakenberg with kappa = 100 (Sec. 3.4.1) and the
+    Allen-Cahn shrinking circle (Sec. 3.1.1): iterations per step beside the paper's
+    counts, time per step and throughput."""
+    import numpy as np
+    n = min(steps, 20)
+    cases = {
+        "fch_sec3.3": (rd.make_problem("fch", 128, L=2 * np.pi, diff=(0.18 ** 2,)), wl.fch_example_field(128),
+                       1e-3, dict(tol=0.5e-5, tau_u=0.58, tau_p=0.58, max_iter=3000), ("fp64",)),
+        "schnakenberg_sec3.4.1": (rd.make_problem("schnakenberg", 128, bc="neumann", diff=(0.05, 1.0), a=0.1305,
+                                                  sb=0.7695, kappa=100.0), wl.schnakenberg_example_field(128),
+                                  1.0 / 5000, dict(tol=1e-7, tau_u=0.9, tau_p=0.9), ("fp64", "mixed")),
+        "allen_cahn_circle_sec3.1.1": (rd.make_problem("allen_cahn", 128, L=0.5, diff=(0.01,), b=100.0),
+                                       wl.circle_example_field(128), 1e-3, dict(tol=1e-7, tau_u=0.5, tau_p=0.5),
+                                       ("fp64", "mixed")),
+    }
+    out = {}
+    for name, (p, u0_np, ht, kw, precs) in cases.items():
+        u0 = torch.tensor(u0_np, dtype=torch.float64, device="cuda")
+        out[name] = {}
+        for prec in precs:
+            o = rd.make_opts(precision=prec, **kw)
+            a = u0.clone()
+            b = torch.empty_like(a)
+            ctx.step(a, ht, p, o, out=b)
+            torch.cuda.synchronize()
+            iters, lat = [], []
+            t0 = time.perf_counter()
+            for _ in range(n):
+                ts = time.perf_counter()
+                _, info = ctx.step(a, ht, p, o, out=b)
+                lat.append(time.perf_counter() - ts)
+                iters.append(info["iters"])
+                a, b = b, a
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            pts = u0_np.shape[-1] ** 2
+            out[name][prec] = dict(steps=n, iters_per_step=sum(iters) / n, iters_first=iters[0],
+                                   iters_last=iters[-1], ms_per_step=1e3 * wall / n,
+                                   p50_ms=1e3 * percentile(lat, 50), pt_iters_per_s=pts * sum(iters) / wall)
+    out["paper_counts"] = {"schnakenberg_sec3.4.1": "about 30 iterations per step",
+                           "allen_cahn_circle_sec3.1.1": "fewer than 200 iterations per step"}
+    return out
+
+
 def grid3d_leg(ctx, rd, torch, wl, steps):
     """The 128^3 Allen-Cahn workload (7-point Laplacian, 3-D FFT preconditioner),
     both precisions, the workload's step count (or ``steps`` if smaller)."""
@@ -366,6 +412,11 @@ def main():
     hbm4096 = hbm_leg(ctx, rd, torch, wl, args.steps)
     log("  %s" % json.dumps({p: hbm4096[p]["pt_iters_per_s"] for p in ("fp64", "mixed")}))
 
+    log("paper examples (128^2): FCH, Schnakenberg kappa = 100, Allen-Cahn circle")
+    examples = paper_examples_leg(ctx, rd, torch, wl, args.steps)
+    log("  %s" % json.dumps({k: {p: v[p]["iters_per_step"] for p in v} for k, v in examples.items()
+                             if k != "paper_counts"}))
+
     log("3-D grid: 128^3 Allen-Cahn")
     grid3d = grid3d_leg(ctx, rd, torch, wl, args.steps)
     log("  %s" % json.dumps(grid3d))
@@ -398,7 +449,7 @@ def main():
         "mixed": mx, "fp64": f64,
         "speedup_mixed_vs_fp64": f64["wall_s"] / mx["wall_s"],
         "accuracy": accuracy, "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu, "serving": serving,
-        "adaptive": adaptive, "grid3d": grid3d, "hbm4096": hbm4096,
+        "adaptive": adaptive, "grid3d": grid3d, "hbm4096": hbm4096, "paper_examples": examples,
     }
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -112,3 +112,27 @@ def grid_points(cfg):
 def log2_exact(n):
     k = int(round(math.log2(n)))
     return k if 2 ** k == n else None
+
+
+# ---- the paper's own examples (analytic initial states), used by the measurement
+def fch_example_field(N, L=2 * np.pi):
+    """Sec. 3.3: two bumps on the periodic square [0, L)^2, h = L / N."""
+    x = np.arange(N) * (L / N)
+    X, Y = np.meshgrid(x, x)
+    return 2 * np.exp(np.sin(X) + np.sin(Y) - 2) + 2.2 * np.exp(-np.sin(X) - np.sin(Y) - 2) - 1
+
+
+def schnakenberg_example_field(N, a=0.1305, b=0.7695):
+    """Sec. 3.4.1: the steady state (a + b, b / (a + b)^2) with a small Gaussian bump
+    on u, cell-centred unit square."""
+    x = (np.arange(N) + 0.5) / N
+    X, Y = np.meshgrid(x, x)
+    return np.stack([a + b + 1e-3 * np.exp(-100 * ((X - 1 / 3) ** 2 + (Y - 1 / 2) ** 2)),
+                     np.full((N, N), b / (a + b) ** 2)])
+
+
+def circle_example_field(N, L=0.5, r0=0.2):
+    """Sec. 3.1.1: +1 inside a circle of radius r0, -1 outside, on [-L/2, L/2)^2."""
+    x = -L / 2 + np.arange(N) * (L / N)
+    X, Y = np.meshgrid(x, x)
+    return np.where(X ** 2 + Y ** 2 < r0 ** 2, 1.0, -1.0)

@@ -338,6 +338,15 @@ def grid3d_leg(ctx, rd, torch, wl, steps):
     out["mixed_vs_fp64_final_maxabs"] = float((finals["mixed"] - finals["fp64"]).abs().max().item())
     out["speedup_mixed_vs_fp64"] = out["fp64"]["wall_s"] / out["mixed"]["wall_s"]
     out["kernels"] = {prec: kernel_table(ctx, rd, cfg, u0, prec, cfg["N"] ** 3) for prec in ("fp64", "mixed")}
+    # the largest 3-D grid, the same parameters: rate and kernels at 16.8 M points
+    big = dict(cfg, N=256)
+    u1 = torch.tensor(wl.initial_field(big), dtype=torch.float64, device="cuda")
+    out["n256"] = {}
+    for prec in ("fp64", "mixed"):
+        out["n256"][prec], _, _ = run_precision(ctx, rd, torch, big, u1, prec, min(n, 10), 1)
+        out["n256"][prec]["kernels"] = kernel_table(ctx, rd, big, u1, prec, 256 ** 3)
+    del u1
+    torch.cuda.empty_cache()
     return out
 
 

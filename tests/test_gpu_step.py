@@ -185,3 +185,21 @@ def test_zero_iterations_when_start_is_converged(ctx, rd):
     Ug, info = ctx.step(dev(U), cfg["ht"], rd.problem_from_config(cfg), gpu_opts(rd, cfg, tol=1e-9))
     assert info["iters"] == 0 and info["status"] == "ok"
     assert np.array_equal(Ug.cpu().numpy(), U)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_in_place_step_equals_out_of_place(ctx, rd, precision, dim):
+    """u_n and u_np1 may alias: the in-place step gives bitwise the out-of-place result."""
+    N = 64 if dim == 2 else 32
+    cfg = small_cfg("allen_cahn", N, "periodic")
+    cfg["dim"] = dim
+    U0 = wl.uniform_field(N, -0.5, 0.5, 14, dim)
+    p = rd.problem_from_config(cfg)
+    o = gpu_opts(rd, cfg, precision, tol=1e-8)
+    ref, i_ref = ctx.step(dev(U0), cfg["ht"], p, o)
+    u = dev(U0)
+    out, info = ctx.step(u, cfg["ht"], p, o, out=u)
+    assert out.data_ptr() == u.data_ptr()
+    assert info["iters"] == i_ref["iters"] and info["status"] == "ok"
+    assert np.array_equal(u.cpu().numpy(), ref.cpu().numpy())

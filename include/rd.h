@@ -15,9 +15,9 @@
  *
  * from U_0 = U^k, P_0 = 0, stopped when ||Res(U_n)||_2 <= tol with Res = F / h_t
  * (Sec. 2.1, "Stopping criterion"; for two components the component norms are
- * added, Sec. 3.4.1).  G = (I - alpha Lap + beta Lap^2)^2 is inverted by a 2-D FFT
- * (periodic grids) or a 2-D DCT-II (Neumann grids, Remark 1); on 3-D grids by the
- * 3-D transforms.
+ * added, Sec. 3.4.1).  G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2 (gamma only for
+ * the sixth-order equation of Sec. 3.3) is inverted by a 2-D FFT (periodic grids) or a
+ * 2-D DCT-II (Neumann grids, Remark 1); on 3-D grids by the 3-D transforms.
  *
  * Conventions for every entry point:
  *   - Array arguments documented as DEVICE are device (HBM) pointers; HOST ones are
@@ -54,8 +54,8 @@ typedef enum {
 typedef enum { RD_BC_PERIODIC = 0, RD_BC_NEUMANN = 1 } rd_bc;
 
 /* Linear operator of F.  RD_OP_LAP5: +lambda Lap with the 5-point Laplacian (Sec. 2.1;
- * on a 3-D grid the 7-point Laplacian;
- * periodic block-circulant form, or the Neumann L_1/L_2 form of Remark 1, eq. 24).
+ * periodic block-circulant form, or the Neumann L_1/L_2 form of Remark 1, eq. 24); on
+ * a 3-D grid the 7-point Laplacian.
  * RD_OP_BIHARM13: -lambda Lap Lap with the 13-point stencil (= 5-point squared; Sec. 3.2).
  * RD_OP_FCH6: the sixth-order functionalized Cahn-Hilliard operator of Sec. 3.3 (nested
  * 5-point Laplacians, 25-point reach), with RD_RX_FCH only; FP64 precision only.        */
@@ -190,9 +190,10 @@ rd_status rd_advance(void *ctx, const rd_problem *prob, const rd_opts *opts, con
  * *res_l2 (HOST) receives ||W / h_t||_2 summed over components.  Synchronises.          */
 rd_status rd_residual(void *ctx, const rd_problem *prob, double h_t, const double *u,
                       const double *uk, double *w, void *hip_stream, double *res_l2);
-/* Y = G^-1 W with G = (I - alpha Lap + beta Lap^2)^2 per component as the equation
- * implies (Sec. 2.1 "Choosing the matrix G"; Remark 1 for Neumann).  w, y: DEVICE.
- * precision RD_FP64 or RD_FP32_MIXED (FP32 transforms).  Synchronises.                    */
+/* Y = G^-1 W with G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2 per component as the
+ * equation implies (Sec. 2.1 "Choosing the matrix G"; Remark 1 for Neumann; Sec. 3.3 for
+ * gamma).  w, y: DEVICE, [c][N][N] or [c][N][N][N].  precision RD_FP64 or RD_FP32_MIXED
+ * (FP32 transforms; FP64 only for RD_OP_FCH6).  Synchronises.                               */
 rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_t precision,
                            const double *w, double *y, void *hip_stream);
 /* Pointwise reaction prox (the implicit reaction-only step, a predictor for U_0;
@@ -202,7 +203,7 @@ rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *c
                   void *hip_stream);
 
 /* ---- instrumentation ------------------------------------------------------------- */
-/* Time the four kernels of one Algorithm-1 iteration on hip_stream: prepares the step
+/* Time the kernels of one Algorithm-1 iteration on hip_stream: prepares the step
  * for u_n (DEVICE) like rd_step (stop rules disabled), runs one untimed iteration, then
  * `reps` iterations in the solver's launch order, back to back, each launch recording
  * a start and a stop HIP event in its own dispatch packets (the kernel's begin and end
@@ -210,9 +211,9 @@ rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *c
  * (HOST, 4 doubles on a 2-D grid, 6 on a 3-D one) receives the mean duration per launch
  * in milliseconds of, 2-D: column pass (with the stop decision of the preceding row
  * pass), inverse row pass + dual update, primal update, residual + forward row pass;
- * 3-D: forward y-line pass, z-line pass (forward, symbol, inverse), inverse y-line
- * pass, inverse x-row pass + dual update, primal update, residual + forward x-row pass
- * with its stop decision.  Synchronises.                                               */
+ * 3-D: forward y-line pass (with the stop decision of the preceding row pass), z-line
+ * pass (forward, symbol, inverse), inverse y-line pass, inverse x-row pass + dual
+ * update, primal update, residual + forward x-row pass.  Synchronises.                 */
 rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
                                const double *u_n, int32_t reps, void *hip_stream, double *ms_out);
 
@@ -221,7 +222,7 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
  * memory.  Each pump round admits queued trajectories (arrival order, while the budget
  * allows), starts the next submitted step of every idle admitted trajectory, and
  * advances every running step by one round of iterations.  Running steps that share
- * (precision, N, boundary condition, equation family) form a batch group: one launch
+ * (precision, N, dimension, boundary condition, equation family) form a batch group: one launch
  * per kernel covers all of them (one workgroup row per step), and different groups run
  * on separate streams so that they overlap on the device.  A step's arithmetic does not
  * depend on what else is in the batch: each result equals the one rd_step returns.
@@ -232,7 +233,7 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
  * trajectory is admitted while resident + its workspace <= budget, and always when
  * nothing is resident (so a single request larger than the budget still runs).        */
 rd_status rd_serve_set_budget(void *ctx, size_t bytes);
-/* Open a trajectory: copies u0 (DEVICE, [c][N][N] FP64) into a resident copy, ordered
+/* Open a trajectory: copies u0 (DEVICE, FP64, [c][N][N] or [c][N][N][N]) into a resident copy, ordered
  * after prior work on hip_stream, and synchronises it.  *out (HOST) receives the handle.
  * Workspace memory is reserved only at admission, by rd_serve_pump.                    */
 rd_status rd_traj_open(void *ctx, const rd_problem *prob, const rd_opts *opts,

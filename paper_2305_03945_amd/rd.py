@@ -194,10 +194,22 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _dptr(t):
+def field_size(problem):
+    """FP64 values of one field of the problem: components x grid points."""
+    ncomp = 2 if problem.rx == RD_RX_SCHNAKENBERG else 1
+    return ncomp * problem.nx * problem.ny * (problem.nz if problem.nz > 1 else 1)
+
+
+def _dptr(t, problem=None, numel=None):
+    """The device address of a contiguous float64 tensor, after checking that it holds
+    exactly one field of `problem` (or `numel` values): the library reads and writes
+    whole fields through the pointer and cannot check the size itself."""
     import torch
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("expected a contiguous float64 device tensor")
+    want = field_size(problem) if problem is not None else numel
+    if want is not None and t.numel() != want:
+        raise ValueError("tensor holds %d values, the problem's field %d" % (t.numel(), want))
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -231,7 +243,7 @@ class Context:
         if out is None:
             out = torch.empty_like(u)
         info = Info()
-        code = _lib.rd_step(self._h, ctypes.byref(problem), ctypes.byref(opts), float(ht), _dptr(u), _dptr(out),
+        code = _lib.rd_step(self._h, ctypes.byref(problem), ctypes.byref(opts), float(ht), _dptr(u, problem), _dptr(out, problem),
                             _stream_ptr(stream), ctypes.byref(info))
         if code in raise_on:
             raise RDError(code, "rd_step")
@@ -242,7 +254,7 @@ class Context:
         import torch
         w = torch.empty_like(u)
         res = ctypes.c_double()
-        _check(_lib.rd_residual(self._h, ctypes.byref(problem), float(ht), _dptr(u), _dptr(uk), _dptr(w),
+        _check(_lib.rd_residual(self._h, ctypes.byref(problem), float(ht), _dptr(u, problem), _dptr(uk, problem), _dptr(w, problem),
                                 _stream_ptr(stream), ctypes.byref(res)), "rd_residual")
         return w, res.value
 
@@ -250,21 +262,21 @@ class Context:
         import torch
         y = torch.empty_like(w)
         prec = RD_FP64 if precision == "fp64" else RD_FP32_MIXED
-        _check(_lib.rd_precond_solve(self._h, ctypes.byref(problem), float(ht), prec, _dptr(w), _dptr(y),
+        _check(_lib.rd_precond_solve(self._h, ctypes.byref(problem), float(ht), prec, _dptr(w, problem), _dptr(y, problem),
                                      _stream_ptr(stream)), "rd_precond_solve")
         return y
 
     def prox(self, c, ht, problem, stream=None):
         import torch
         u = torch.empty_like(c)
-        _check(_lib.rd_prox(self._h, ctypes.byref(problem), float(ht), _dptr(c), _dptr(u), _stream_ptr(stream)),
+        _check(_lib.rd_prox(self._h, ctypes.byref(problem), float(ht), _dptr(c, problem), _dptr(u, problem), _stream_ptr(stream)),
                "rd_prox")
         return u
 
     def profile_iteration(self, u, ht, problem, opts, reps=20, stream=None):
         """Mean launch duration (ms) of each kernel of one iteration, HIP events on `stream`."""
         out = (ctypes.c_double * 6)()
-        _check(_lib.rd_profile_iteration(self._h, ctypes.byref(problem), ctypes.byref(opts), float(ht), _dptr(u),
+        _check(_lib.rd_profile_iteration(self._h, ctypes.byref(problem), ctypes.byref(opts), float(ht), _dptr(u, problem),
                                          int(reps), _stream_ptr(stream), out), "rd_profile_iteration")
         names = ("yfwd", "zsym", "yinv", "rowinv", "upd", "rowfwd") if problem.nz > 1 else \
             ("cols", "rowinv", "upd", "rowfwd")
@@ -278,7 +290,7 @@ class Context:
         ti = (ctypes.c_int32 * max(trace_cap, 1))()
         tk = (ctypes.c_int32 * max(trace_cap, 1))()
         code = _lib.rd_advance(self._h, ctypes.byref(problem), ctypes.byref(opts), ctypes.byref(adapt), float(t0),
-                               float(t_end), _dptr(u), _stream_ptr(stream), ctypes.byref(info), th, ti, tk,
+                               float(t_end), _dptr(u, problem), _stream_ptr(stream), ctypes.byref(info), th, ti, tk,
                                int(trace_cap))
         _check(code, "rd_advance", allowed=(RD_OK, RD_E_NOCONV))
         n = min(trace_cap, info.accepted + info.rejected)
@@ -290,7 +302,7 @@ class Context:
 
     def open(self, problem, opts, u0, stream=None):
         h = ctypes.c_void_p()
-        _check(_lib.rd_traj_open(self._h, ctypes.byref(problem), ctypes.byref(opts), _dptr(u0),
+        _check(_lib.rd_traj_open(self._h, ctypes.byref(problem), ctypes.byref(opts), _dptr(u0, problem),
                                  _stream_ptr(stream), ctypes.byref(h)), "rd_traj_open")
         return Trajectory(self, h, tuple(u0.shape))
 
@@ -317,6 +329,9 @@ class Trajectory:
         self.ctx = ctx
         self._h = handle
         self.shape = shape
+        self.numel = 1
+        for n in shape:
+            self.numel *= int(n)
 
     def submit(self, ht):
         t = ctypes.c_uint64()
@@ -327,7 +342,7 @@ class Trajectory:
         import torch
         if out is None:
             out = torch.empty(self.shape, dtype=torch.float64, device="cuda")
-        _check(_lib.rd_traj_read(self._h, _dptr(out), _stream_ptr(stream)), "rd_traj_read")
+        _check(_lib.rd_traj_read(self._h, _dptr(out, numel=self.numel), _stream_ptr(stream)), "rd_traj_read")
         return out
 
     def close(self):

@@ -155,8 +155,13 @@ def test_3d_argument_rules(ctx, rd):
         ctx.prox(u, 1e-3, p)
     bad = rd.make_problem("allen_cahn", 16, dim=3)
     bad.nz = 32
-    with pytest.raises(rd.RDError):
-        ctx.step(u, 1e-3, bad, rd.make_opts())
+    ubad = torch.zeros((32, 16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(rd.RDError):     # the library refuses nz != nx
+        ctx.step(ubad, 1e-3, bad, rd.make_opts())
+    with pytest.raises(ValueError):     # the binding refuses a tensor of the wrong size
+        ctx.step(u[:8].contiguous(), 1e-3, p, rd.make_opts())
+    with pytest.raises(ValueError):
+        ctx.precond_solve(torch.zeros((16, 16), dtype=torch.float64, device="cuda"), 1e-3, p)
     big = rd.make_problem("allen_cahn", 512, dim=3)
     assert rd.footprint_bytes(big, rd.make_opts()) == 0
     ch = rd.make_problem("cahn_hilliard", 16, dim=3)

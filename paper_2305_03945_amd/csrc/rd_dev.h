@@ -147,10 +147,14 @@ __device__ __forceinline__ int dct_pos(int x, int N) { return (x & 1) ? (N - 1 -
 // pair is one transform, so R = 2 * teams keeps every team busy (R N = 32 NT
 // reals of LDS per component).  At least 2, at most N/4 (so that every grid
 // spans at least four workgroups), and for two components at most half that.
+// Where one team spans the workgroup (N >= 16 NT), FP32 workgroups take two
+// row pairs, transformed in turn, so that the spectrum tiles are four rows high
+// and the column pass reads 128-byte runs.
 template <typename T, int LOGN, int C> constexpr int rows_per_block() {
     constexpr int N = 1 << LOGN;
     constexpr int teams = (N / 16 >= NT) ? 1 : NT / (N / 16);
-    constexpr int want = 2 * teams / C;
+    constexpr int pairs = (N / 16 >= NT && sizeof(T) == 4) ? 2 : 1;
+    constexpr int want = 2 * teams * pairs / C;
     constexpr int cap = N / 4;
     constexpr int r = want < 2 ? 2 : (want > cap ? cap : want);
     return r;

@@ -217,3 +217,56 @@ def test_poll_and_argument_errors(rd):
         t.close()
     finally:
         ctx.close()
+
+
+def test_fch_and_3d_trajectories_in_the_mix(rd):
+    """Sixth-order (FP64) and 3-D trajectories served beside 2-D ones: each result equals
+    its steps run alone through rd_step, bitwise, with the same iteration counts."""
+    import math
+    fch = rd.make_problem("fch", 64, L=2 * math.pi, diff=(0.18 ** 2,))
+    fch_o = rd.make_opts(tol=1e-6, tau_u=0.58, tau_p=0.58, max_iter=5000)
+    x = np.arange(64) * (2 * math.pi / 64)
+    X, Y = np.meshgrid(x, x)
+    fch_u0 = 2 * np.exp(np.sin(X) + np.sin(Y) - 2) + 2.2 * np.exp(-np.sin(X) - np.sin(Y) - 2) - 1
+    c3 = dict(small_cfg("allen_cahn", 32, "neumann"), dim=3)
+    p3 = rd.problem_from_config(c3)
+    o3 = opts_for(rd, c3, "mixed")
+    u3 = wl.uniform_field(32, -0.5, 0.5, 44, 3)
+    c2 = small_cfg("schnakenberg", 64, "periodic")
+    jobs = [(fch, fch_o, fch_u0, (1e-3, 1e-3)), (p3, o3, u3, (1e-3, 2e-3)),
+            (rd.problem_from_config(c2), opts_for(rd, c2, "mixed"), wl.initial_field(c2, N=64, seed=45), (1e-3,))]
+    alone = []
+    actx = rd.Context(0)
+    try:
+        for p, o, u0, hts in jobs:
+            u, infos = dev(u0), []
+            for ht in hts:
+                u, info = actx.step(u, ht, p, o)
+                infos.append(info)
+            alone.append((u.cpu().numpy(), infos))
+    finally:
+        actx.close()
+    ctx = rd.Context(0)
+    try:
+        trajs = [ctx.open(p, o, dev(u0)) for p, o, u0, _ in jobs]
+        tickets = [[t.submit(ht) for ht in job[3]] for t, job in zip(trajs, jobs)]
+        infos = {}
+
+        def done():
+            for tl in tickets:
+                for tk in tl:
+                    if tk not in infos:
+                        i = ctx.poll(tk)
+                        if i is not None:
+                            infos[tk] = i
+            return len(infos) == sum(len(tl) for tl in tickets)
+
+        pump_until(ctx, done)
+        for t, tl, (ref, ref_infos) in zip(trajs, tickets, alone):
+            assert np.array_equal(t.read().cpu().numpy(), ref)
+            for tk, ai in zip(tl, ref_infos):
+                assert infos[tk]["status"] == "ok"
+                assert (infos[tk]["iters"], infos[tk]["outer"]) == (ai["iters"], ai["outer"])
+            t.close()
+    finally:
+        ctx.close()

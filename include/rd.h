@@ -99,7 +99,8 @@ typedef enum { RD_INIT_PREV = 0, RD_INIT_PROX = 1 } rd_init;
 typedef struct {
     double tol;              /* stop when ||F(U)/h_t||_2 (summed over components) <= tol   */
     int32_t max_iter;        /* PDHG iterations per step (FP64), or inner iterations per outer
-                                pass (mixed)                                                 */
+                                pass (mixed); 0: no iteration, the step returns U^k with
+                                RD_E_NOCONV unless U^k already meets tol                     */
     int32_t max_outer;       /* mixed only: outer FP64 correction passes                     */
     double tau_u, tau_p;     /* PDHG step sizes                                              */
     double omega;            /* extrapolation coefficient (the paper uses 1, Sec. 3)         */

@@ -350,7 +350,7 @@ __device__ __forceinline__ void finalize(SlotRef s, const double *sumsq, const d
         int odone = 1, status = ST_OK;
         if (!fin || res > GROWTH_LIMIT * st->res0) status = ST_NONFINITE;
         else if (res <= s.tol) status = ST_OK;
-        else if (outer >= s.max_outer) status = ST_NOCONV;
+        else if (outer >= s.max_outer || s.max_iter <= 0) status = ST_NOCONV;
         else odone = 0;
         st->status = status;
         st->outer_done = odone;

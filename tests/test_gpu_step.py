@@ -203,3 +203,56 @@ def test_in_place_step_equals_out_of_place(ctx, rd, precision, dim):
     assert out.data_ptr() == u.data_ptr()
     assert info["iters"] == i_ref["iters"] and info["status"] == "ok"
     assert np.array_equal(u.cpu().numpy(), ref.cpu().numpy())
+
+
+def test_invalid_problems_rejected_before_any_device_work(ctx, rd):
+    """Shapes and operator/reaction pairs the library does not take: rd_footprint_bytes
+    is 0 and rd_step returns RD_E_INVALID, without touching the (one-value) buffers."""
+    import ctypes
+    import torch
+    base = dict(kind="allen_cahn", N=64)
+    cases = []
+    for N in (0, 8, 48, 8192):                       # empty, below 16, not a power of two, above 4096
+        cases.append(rd.make_problem("allen_cahn", N))
+    p = rd.make_problem("allen_cahn", 64); p.ny = 32; cases.append(p)       # not square
+    p = rd.make_problem("allen_cahn", 64); p.ly = 2.0; cases.append(p)      # unequal sides
+    p = rd.make_problem("allen_cahn", 64); p.lx = p.ly = 0.0; cases.append(p)
+    p = rd.make_problem("allen_cahn", 64); p.bc = 7; cases.append(p)
+    p = rd.make_problem("allen_cahn", 64); p.rx = rd.RD_RX_CAHN_HILLIARD; cases.append(p)   # LAP5 + CH
+    p = rd.make_problem("allen_cahn", 64); p.diff[0] = -1.0; cases.append(p)
+    p = rd.make_problem("allen_cahn", 64); p.nz = -1; cases.append(p)
+    p = rd.make_problem("cahn_hilliard", 64, dim=3); cases.append(p)        # no 13-point 3-D form
+    p = rd.make_problem("allen_cahn", 512, dim=3); cases.append(p)          # 3-D above 256
+    one = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ptr = ctypes.c_void_p(one.data_ptr())
+    o = rd.make_opts()
+    for p in cases:
+        assert rd.footprint_bytes(p, o) == 0
+        info = rd.Info()
+        code = rd._lib.rd_step(ctx._h, ctypes.byref(p), ctypes.byref(o), ctypes.c_double(1e-3), ptr, ptr,
+                               rd._stream_ptr(None), ctypes.byref(info))
+        assert code == rd.RD_E_INVALID, (p.nx, p.ny, p.nz, p.op, p.rx)
+
+
+def test_degenerate_steps(ctx, rd):
+    """A vanishing step size (h_t = 1e-9; the plain norm's round-off floor, about
+    eps |U| N / h_t, sets the tolerance) moves U by O(h_t) in a few iterations, as in the
+    oracle; max_iter = 0 returns U^k unchanged with status noconv; both precisions."""
+    cfg = small_cfg("allen_cahn", 64, "periodic")
+    U = wl.initial_field(cfg, N=64, seed=15)
+    p = rd.problem_from_config(cfg)
+    op = oracle_problem(cfg)
+    drive = np.abs(oeq.F(op, U, U, 1.0)).max()          # max |lambda Lap U + f(U)|
+    ht, tol = 1e-9, 1e-3
+    r = opdhg.step(op, U, ht, oracle_opts(cfg, tol=tol))
+    assert r.iters <= 10
+    for precision in ("fp64", "mixed"):
+        out, info = ctx.step(dev(U), ht, p, gpu_opts(rd, cfg, precision, tol=tol))
+        assert info["status"] == "ok" and info["iters"] <= 20, info
+        if precision == "fp64":
+            assert info["iters"] == r.iters
+            assert max_abs(out.cpu().numpy(), r.U) <= 1e-10
+        assert max_abs(out.cpu().numpy(), U) <= 2 * ht * drive
+        out, info = ctx.step(dev(U), cfg["ht"], p, gpu_opts(rd, cfg, precision, max_iter=0))
+        assert info["status"] == "noconv" and info["iters"] == 0, info
+        assert np.array_equal(out.cpu().numpy(), U)

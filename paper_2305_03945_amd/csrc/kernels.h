@@ -762,6 +762,11 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
 // N/16 threads.  CB is chosen so that the CB x R block of a spectrum tile it
 // reads is at least 128 bytes (and the workgroup at least one wave), as far as
 // 156 KB of LDS (of the 160 KB a gfx950 workgroup may hold) and 1024 threads allow.
+// LDS of one column of a column-pass workgroup: a transform region plus the
+// spacing between the regions of the teams of one wave (see cols_regs).
+constexpr int COL_TEAM_PAD = 8;
+template <int LOGN> constexpr int col_region() { return lds_region<LOGN>() + COL_TEAM_PAD; }
+
 template <typename T, int LOGN, int C> constexpr int col_jobs() {
     constexpr int N = 1 << LOGN;
     constexpr int R = rows_per_block<T, LOGN, C>();
@@ -771,7 +776,7 @@ template <typename T, int LOGN, int C> constexpr int col_jobs() {
     constexpr int want = by_tile > by_wave ? by_tile : by_wave;
     // LDS (<= 156 KB, leaving room for the decision lanes) and threads (<= 1024)
     // bound it from above
-    constexpr int by_lds = 159744 / (lds_region<LOGN>() * (int)sizeof(cplx<T>));
+    constexpr int by_lds = 159744 / (col_region<LOGN>() * (int)sizeof(cplx<T>));
     constexpr int by_thr = 1024 / (N / 16 >= 1 ? N / 16 : 1);
     constexpr int cap = by_lds < by_thr ? by_lds : by_thr;
     constexpr int cb0 = want < cap ? want : cap;
@@ -784,7 +789,7 @@ template <typename T, int LOGN, int C> constexpr int col_threads() { return col_
 // the extra decision workgroup of a launch that fills every CU starts at once --
 // where their LDS fits twice in the CU's 160 KB; otherwise one.
 template <typename T, int LOGN, int C> constexpr int col_waves_per_eu() {
-    constexpr int lds = col_jobs<T, LOGN, C>() * lds_region<LOGN>() * (int)sizeof(cplx<T>);
+    constexpr int lds = col_jobs<T, LOGN, C>() * col_region<LOGN>() * (int)sizeof(cplx<T>);
     constexpr int per_cu = 2 * lds + 4096 <= 163840 ? 2 : 1;
     constexpr int w = per_cu * col_threads<T, LOGN, C>() / 64 / 4;
     return w < 1 ? 1 : w;
@@ -796,13 +801,15 @@ template <typename T, int LOGN, int C> constexpr int col_waves_per_eu() {
 // on the same registers, so LDS is touched only between passes.  Lanes are laid
 // out so that R*CB consecutive lanes read R consecutive rows of the CB columns
 // of the block, one contiguous run of the tile layout.  Column 0 of a component
-// (which couples bins l and N - l) takes the LDS path instead.  Used for FP64:
-// measured at N = 2048 it takes the column pass from 26 to 21 us, while the FP32
-// pass, whose 16-byte tile loads carry two values each, is faster through LDS.
+// (which couples bins l and N - l) takes the LDS path instead.  A wave then holds
+// several teams, which would hit the same LDS banks at the same offsets of their
+// regions: team regions are spaced COL_TEAM_PAD complex values apart beyond the
+// region size (64 bytes in FP32: 16 banks).  At N = 2048 the column pass takes
+// 21 instead of 26 us (FP64) and 17.1 instead of 18.2 us (FP32).
 template <typename T, int LOGN, int C> constexpr bool cols_in_regs() {
     constexpr int TPF = (1 << LOGN) / 16;
     constexpr int R = rows_per_block<T, LOGN, C>();
-    return sizeof(T) == 8 && npasses16<LOGN>() >= 2 && TPF >= R && TPF % R == 0;
+    return npasses16<LOGN>() >= 2 && TPF >= R && TPF % R == 0;
 }
 
 template <typename T, int LOGN, int C, int CB>
@@ -814,7 +821,7 @@ __device__ __forceinline__ void cols_regs(SlotRef s, int c, int kx0, cplx<T> *S,
     const int team = (idx / R) % CB;
     const int t = (idx / (R * CB)) * R + idx % R;
     const int kx = kx0 + team;
-    cplx<T> *x = buf + team * lds_region<LOGN>();
+    cplx<T> *x = buf + team * col_region<LOGN>();
     // element t + r N/16 of the column sits r * (N/16) * (N/2) slots after element t
     const int o0 = (int)spec_off<R>(c, t, kx, N);
     constexpr int STRIDE = TPF * H;
@@ -842,12 +849,18 @@ __device__ __forceinline__ void cols_regs(SlotRef s, int c, int kx0, cplx<T> *S,
         }
     }
     __syncthreads();   // the last forward pass has read x
-    // gather the twiddles again rather than keeping them live across the symbol
+    // gather the twiddles again rather than keeping them live across the symbol,
+    // and recompute the LDS addresses of the inverse passes rather than keeping the
+    // forward ones (an empty asm hides that t is unchanged; without it the FP32
+    // pass spills them)
     __asm__ volatile("" ::: "memory");
     {
+        int t2 = t;
+        __asm__ volatile("" : "+v"(t2));
+        cplx<T> *x2 = buf + ((threadIdx.x / R) % CB) * col_region<LOGN>();
         Tw16<T, LOGN> twr;
-        load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw, t);
-        fft16_regs<T, LOGN, +1>(x, t, twr, v);
+        load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw, t2);
+        fft16_regs<T, LOGN, +1>(x2, t2, twr, v);
     }
     const auto So = gp((v2_t *)S);
 #pragma unroll
@@ -872,7 +885,7 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>()), (col_waves_per_eu<T, L
     constexpr int NTH = col_threads<T, LOGN, C>();
     constexpr int CB = col_jobs<T, LOGN, C>();
     constexpr int R = rows_per_block<T, LOGN, C>();
-    __shared__ cplx<T> buf[CB * lds_region<LOGN>()];
+    __shared__ cplx<T> buf[CB * col_region<LOGN>()];
     __shared__ double lanes[FIN == FIN_NONE ? 1 : 64 * 2 * C];
     SlotRef s = slot_of(slots);
     StateRef sst = state_of(s);

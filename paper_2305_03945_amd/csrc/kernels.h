@@ -238,6 +238,34 @@ __device__ __forceinline__ void load_win(Win<T, HY> &w, gptr_t<const T> f, int y
     }
 }
 
+// Window of two adjacent rows y, y + 1 (four points each) for a stencil of reach
+// HY: rows y - HY .. y + 1 + HY, each with the x-halo that an output row at its
+// distance needs.  Shared rows are loaded once.
+template <typename T, int HY> struct Win2 {
+    T v[2 * HY + 2][4 + 2 * HY];
+    // row j (0: y, 1: y + 1) of the output pair
+    __device__ __forceinline__ T at(int j, int k, int dy, int dx) const { return v[j + dy + HY][HY + dx + k]; }
+};
+
+template <typename T, int BC, int LOGN, int HY>
+__device__ __forceinline__ void load_win2(Win2<T, HY> &w, gptr_t<const T> f, int y, int x0) {
+    constexpr int N = 1 << LOGN;
+#pragma unroll
+    for (int d = -HY; d <= HY + 1; ++d) {
+        const int dist = d < 0 ? -d : (d > 1 ? d - 1 : 0);   // to the nearer output row
+        const int hx = HY - dist;
+        const gptr_t<const T> row = f + (size_t)wrap<BC>(y + d, N) * N;
+        const vec4_t<T> m = *(const gptr_t<const vec4_t<T>>)(row + x0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w.v[d + HY][HY + k] = m[k];
+#pragma unroll
+        for (int h = 1; h <= hx; ++h) {
+            w.v[d + HY][HY - h] = row[wrap<BC>(x0 - h, N)];
+            w.v[d + HY][HY + 3 + h] = row[wrap<BC>(x0 + 3 + h, N)];
+        }
+    }
+}
+
 template <typename T> __device__ __forceinline__ vec4_t<T> load4(gptr_t<const T> p) {
     return *(const gptr_t<const vec4_t<T>>)p;
 }
@@ -576,6 +604,76 @@ __device__ __forceinline__ void produce_W4(SlotRef s, StateRef sst, int y, int x
     }
 }
 
+// produce_W4 for the iteration kinds on two adjacent rows y, y + 1 at once: the
+// rows the two stencils share are loaded once.  wv[j][k][c] receives row j's value
+// at point k; acc as in produce_W4 (both rows).
+template <typename T, int LOGN, int BC, int EQ, int KIND>
+__device__ __forceinline__ void produce_W4x2(SlotRef s, StateRef sst, int y, int x0,
+                                             T (*wv)[4][EQ == EQ_SCHNAK ? 2 : 1], double *acc) {
+    static_assert(KIND == K_ITER64 || KIND == K_INNER32, "two-row producer: iteration kinds only");
+    constexpr int N = 1 << LOGN;
+    constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
+    constexpr size_t NN = (size_t)N * N;
+    constexpr int HY = stencil_hy<EQ>();
+    const int it = sst.iters;
+    const size_t g0 = (size_t)y * N + x0;
+    if constexpr (KIND == K_ITER64) {
+        const auto Un = gp((const double *)s.U[(it + 1) & 1]);
+        Win2<double, HY> wu[C];
+        vec4_t<double> uk[2][C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            load_win2<double, BC, LOGN, HY>(wu[c], Un + c * NN, y, x0);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) uk[j][c] = load4<double>(gp((const double *)s.Uk) + c * NN + g0 + j * N);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double W[C], Uc[C], ukc[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) ukc[c] = uk[j][c][k];
+                eval_F<EQ, double>(s, [&](int c, int dy, int dx) { return wu[c].at(j, k, dy, dx); }, ukc, W, Uc);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    acc[c] += W[c] * W[c];
+                    acc[C + c] += Uc[c] - ukc[c];
+                    wv[j][k][c] = (T)W[c];
+                }
+            }
+    } else {
+        constexpr int HU = EQ == EQ_BIH ? 1 : 0;
+        const auto E = gp((const float *)s.U[(it + 1) & 1]);
+        const auto Ub = gp((const float *)s.Ub32);
+        Win2<float, HY> we[C];
+        Win2<float, HU> wub[C];
+        vec4_t<float> r4[2][C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            load_win2<float, BC, LOGN, HY>(we[c], E + c * NN, y, x0);
+            load_win2<float, BC, LOGN, HU>(wub[c], Ub + c * NN, y, x0);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) r4[j][c] = load4<float>(gp((const float *)s.r32) + c * NN + g0 + j * N);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float rc[C], W[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) rc[c] = r4[j][c][k];
+                eval_Ftilde<EQ>(s, [&](int c, int dy, int dx) { return we[c].at(j, k, dy, dx); },
+                                [&](int c, int dy, int dx) { return wub[c].at(j, k, dy, dx); }, rc, W);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    acc[c] += (double)W[c] * (double)W[c];
+                    wv[j][k][c] = (T)W[c];
+                }
+            }
+    }
+}
+
 // ---------------------------------------------------------------- spectrum layout
 // Per component, N^2/2 complex entries: (kx, y) for kx < N/2 the packed row
 // spectrum slot (periodic) or cosine pair (Neumann) of row y.  Stored in tiles
@@ -711,17 +809,35 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
 #pragma unroll
     for (int k = 0; k < 2 * C; ++k) acc[k] = 0.0;
 
-    // four consecutive points per thread and pass, vector loads
+    if constexpr (KIND == K_ITER64) {
+        // four consecutive points of both rows of a pair per thread: the packed
+        // complex value (row 2p + i row 2p+1) goes to LDS in one write.  FP64 only
+        // (2048^2: 27.7 -> 25.2 us); the FP32 inner pass measured no gain.
 #pragma unroll 2
-    for (int idx = threadIdx.x; idx < R * N / 4; idx += NT) {
-        const int r = idx >> (LOGN - 2), x0 = (idx & (N / 4 - 1)) * 4;
-        T wv[4][C];
-        produce_W4<T, LOGN, BC, EQ, KIND>(s, sst, y0 + r, x0, wv, acc);
+        for (int idx = threadIdx.x; idx < (R / 2) * N / 4; idx += NT) {
+            const int p = idx >> (LOGN - 2), x0 = (idx & (N / 4 - 1)) * 4;
+            T wv[2][4][C];
+            produce_W4x2<T, LOGN, BC, EQ, KIND>(s, sst, y0 + 2 * p, x0, wv, acc);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int pos = (BC == BC_P) ? x0 + k : dct_pos(x0 + k, N);
+            for (int k = 0; k < 4; ++k) {
+                const int pos = (BC == BC_P) ? x0 + k : dct_pos(x0 + k, N);
 #pragma unroll
-            for (int c = 0; c < C; ++c) rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = wv[k][c];
+                for (int c = 0; c < C; ++c) buf[rix<LOGN>(c * R / 2 + p, pos)] = cplx<T>{wv[0][k][c], wv[1][k][c]};
+            }
+        }
+    } else {
+        // four consecutive points per thread and pass, vector loads
+#pragma unroll 2
+        for (int idx = threadIdx.x; idx < R * N / 4; idx += NT) {
+            const int r = idx >> (LOGN - 2), x0 = (idx & (N / 4 - 1)) * 4;
+            T wv[4][C];
+            produce_W4<T, LOGN, BC, EQ, KIND>(s, sst, y0 + r, x0, wv, acc);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int pos = (BC == BC_P) ? x0 + k : dct_pos(x0 + k, N);
+#pragma unroll
+                for (int c = 0; c < C; ++c) rreal<T, LOGN>(buf, c * R / 2 + r / 2, 2 * pos + (r & 1)) = wv[k][c];
+            }
         }
     }
     __syncthreads();

@@ -610,14 +610,70 @@ __device__ __forceinline__ void produce_W4(SlotRef s, StateRef sst, int y, int x
 template <typename T, int LOGN, int BC, int EQ, int KIND>
 __device__ __forceinline__ void produce_W4x2(SlotRef s, StateRef sst, int y, int x0,
                                              T (*wv)[4][EQ == EQ_SCHNAK ? 2 : 1], double *acc) {
-    static_assert(KIND == K_ITER64 || KIND == K_INNER32, "two-row producer: iteration kinds only");
+    static_assert(KIND == K_ITER64 || KIND == K_INNER32 || KIND == K_OUTER_UPD,
+                  "two-row producer: iteration and outer-update kinds");
     constexpr int N = 1 << LOGN;
     constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
     constexpr size_t NN = (size_t)N * N;
     constexpr int HY = stencil_hy<EQ>();
     const int it = sst.iters;
     const size_t g0 = (size_t)y * N + x0;
-    if constexpr (KIND == K_ITER64) {
+    if constexpr (KIND == K_OUTER_UPD) {
+        // U = U_prev + e in FP64 on the two-row window, r = F(U); stores U, its FP32
+        // copy and the FP32 r of both rows
+        const auto Ucur = gp((const double *)s.U64[sst.outer & 1]);
+        Win2<double, HY> wu[C];
+        vec4_t<double> uk[2][C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            load_win2<double, BC, LOGN, HY>(wu[c], Ucur + c * NN, y, x0);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) uk[j][c] = load4<double>(gp((const double *)s.Uk) + c * NN + g0 + j * N);
+        }
+        if (sst.iters > 0) {
+            const auto E = gp((const float *)s.U[sst.iters & 1]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                Win2<float, HY> we;
+                load_win2<float, BC, LOGN, HY>(we, E + c * NN, y, x0);
+#pragma unroll
+                for (int d = 0; d < 2 * HY + 2; ++d) {
+                    const int dd = d - HY;   // offset from row y; the loaded x-halo is load_win2's
+                    const int hx = HY - (dd < 0 ? -dd : (dd > 1 ? dd - 1 : 0));
+#pragma unroll
+                    for (int i = HY - hx; i < HY + 4 + hx; ++i) wu[c].v[d][i] += (double)we.v[d][i];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            vec4_t<double> Uc4[C];
+            vec4_t<float> r4[C], ub4[C];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double W[C], Uc[C], ukc[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) ukc[c] = uk[j][c][k];
+                eval_F<EQ, double>(s, [&](int c, int dy, int dx) { return wu[c].at(j, k, dy, dx); }, ukc, W, Uc);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    acc[c] += W[c] * W[c];
+                    acc[C + c] += Uc[c] - ukc[c];
+                    Uc4[c][k] = Uc[c];
+                    r4[c][k] = (float)W[c];
+                    ub4[c][k] = (float)Uc[c];
+                    wv[j][k][c] = (T)(float)W[c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const size_t g = c * NN + g0 + j * N;
+                store4<double>(gp(s.U64[(sst.outer + 1) & 1]) + g, Uc4[c]);
+                store4<float>(gp(s.r32) + g, r4[c]);
+                store4<float>(gp(s.Ub32) + g, ub4[c]);
+            }
+        }
+    } else if constexpr (KIND == K_ITER64) {
         const auto Un = gp((const double *)s.U[(it + 1) & 1]);
         Win2<double, HY> wu[C];
         vec4_t<double> uk[2][C];
@@ -809,10 +865,11 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
 #pragma unroll
     for (int k = 0; k < 2 * C; ++k) acc[k] = 0.0;
 
-    if constexpr (KIND == K_ITER64) {
+    if constexpr (KIND == K_ITER64 || KIND == K_OUTER_UPD) {
         // four consecutive points of both rows of a pair per thread: the packed
-        // complex value (row 2p + i row 2p+1) goes to LDS in one write.  FP64 only
-        // (2048^2: 27.7 -> 25.2 us); the FP32 inner pass measured no gain.
+        // complex value (row 2p + i row 2p+1) goes to LDS in one write.  The FP64
+        // iteration (2048^2: 27.7 -> 25.2 us) and the mixed outer update; the FP32
+        // inner pass measured no gain.
 #pragma unroll 2
         for (int idx = threadIdx.x; idx < (R / 2) * N / 4; idx += NT) {
             const int p = idx >> (LOGN - 2), x0 = (idx & (N / 4 - 1)) * 4;

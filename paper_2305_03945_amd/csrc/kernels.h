@@ -9,10 +9,12 @@
 //                P~ = P_{n+1} + omega (P_{n+1} - P_n)   (eqs. 21-22)
 //   k_upd        U_{n+1} = U_n - tau_u grad F(U_n)^T P~ (eq. 23 / 32 / Sec. 3.4.1),
 //                reaction derivative at the old U_n
-//   k_row_forward W_{n+1} = F(U_{n+1}), its squared norm, the forward row
-//                transform into S; the last workgroup to finish reduces the
-//                per-workgroup partial sums in a fixed order and takes the stop
-//                decision for the slot (Sec. 2.1 stopping criterion).
+//   k_row_forward W_{n+1} = F(U_{n+1}), per-workgroup partial sums of its squared
+//                norm, the forward row transform into S.
+// The stop decision for the row pass (Sec. 2.1 stopping criterion) is taken by
+// one extra workgroup of the next column pass, which reduces the partial sums
+// in a fixed order while the other workgroups transform; after the initial and
+// outer passes and at the end of a chunk of iterations, by k_finalize.
 // Every kernel first reads the slot's State and returns at once when the slot
 // is finished, so a host may enqueue more iterations than needed.
 #pragma once
@@ -28,8 +30,6 @@ enum {
     K_OUTER_INIT = 3, // mixed: U from u_n, r = F(U) in FP64, inner loop starts
     K_OUTER_UPD = 4   // mixed: U += e (FP64), r = F(U) in FP64, next inner loop
 };
-
-template <typename T> __device__ __forceinline__ T ldg(const T *p) { return *p; }
 
 // ---------------------------------------------------------------- pointwise reaction prox
 // Implicit reaction-only step at one point (predictor for U_0): Allen-Cahn

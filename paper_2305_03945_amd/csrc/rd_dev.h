@@ -4,8 +4,9 @@
 // its workspace pointers and its iteration state.  Every kernel takes an array
 // of slot pointers and processes slot blockIdx.y, so a single step (rd_step) and
 // a batch of same-shape steps of different trajectories (serving) run the same
-// kernels.  All slots of one launch share N, boundary condition, equation family
-// and precision (these are template parameters); everything else is per slot.
+// kernels.  All slots of one launch share N, dimension, boundary condition,
+// equation family and precision (these are template parameters, or select the
+// kernel); everything else is per slot.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

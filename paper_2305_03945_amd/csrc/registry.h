@@ -1,6 +1,7 @@
-// Host-side table of kernel launchers, one entry per (precision mode, log2 N,
-// boundary condition, equation family).  Each instantiation unit fills the
-// entries of one log2 N; the size-independent kernels fill their own fields.
+// Host-side tables of kernel launchers (2-D grids, and 3-D grids for log2 N <=
+// LOGN3_MAX), one entry per (precision mode, log2 N, boundary condition, equation
+// family).  Each instantiation unit fills the entries of one log2 N; the
+// size-independent kernels fill their own fields.
 #pragma once
 #include <hip/hip_runtime.h>
 #include "rd_dev.h"

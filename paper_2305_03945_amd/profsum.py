@@ -68,14 +68,24 @@ def counter_table(path, counter):
     return out
 
 
+def _code_only(text):
+    """Source text without // comments and blank lines (comments do not change kernels)."""
+    out = []
+    for line in text.splitlines():
+        code = re.sub(r"//.*$", "", line).rstrip()
+        if code:
+            out.append(code)
+    return "\n".join(out)
+
+
 def source_hash(root=None):
-    """Hash of the HIP sources: counter figures are valid only for these kernels."""
+    """Hash of the HIP sources (code only): counter figures are valid only for these kernels."""
     root = root or os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(root)):
         if name.endswith((".h", ".hip")):
             h.update(name.encode())
-            h.update(open(os.path.join(root, name), "rb").read())
+            h.update(_code_only(open(os.path.join(root, name)).read()).encode())
     return h.hexdigest()[:16]
 
 

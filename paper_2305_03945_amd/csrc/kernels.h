@@ -276,6 +276,8 @@ template <typename T> __device__ __forceinline__ void store4(gptr_t<T> p, const 
 template <int EQ> constexpr int stencil_hy() { return EQ == EQ_FCH ? 3 : EQ == EQ_BIH ? 2 : 1; }
 
 // ---------------------------------------------------------------- deterministic block sums
+// Workgroup sum of K values per thread, in a fixed order (wave butterflies, then
+// the waves in order); the totals are valid in thread 0 only.
 template <int K> __device__ __forceinline__ void block_sum(double *v, double *scratch /* K * NT/64 */) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -290,14 +292,15 @@ template <int K> __device__ __forceinline__ void block_sum(double *v, double *sc
         for (int k = 0; k < K; ++k) scratch[k * (NT / 64) + wave] = v[k];
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double x = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double x = 0.0;
 #pragma unroll
-        for (int w = 0; w < NT / 64; ++w) x += scratch[k * (NT / 64) + w];
-        v[k] = x;
+            for (int w = 0; w < NT / 64; ++w) x += scratch[k * (NT / 64) + w];
+            v[k] = x;
+        }
     }
-    __syncthreads();
 }
 
 __device__ __forceinline__ bool finite_(double x) { return x == x && x - x == 0.0; }

@@ -412,6 +412,14 @@ def main():
     roofline = dict(bound="hbm", kernel=dom, achieved=round(dk["gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None if traffic is None else round(traffic),
                     traffic_unit="bytes per launch", bytes_per_launch=dk["bytes"], ms_per_launch=dk["ms"])
+    # the whole iteration (all four kernels, back to back) against the same roofline
+    roofline["iteration"] = {}
+    for prec in ("fp64", "mixed"):
+        it_bytes = sum(v["bytes"] for v in kernels[prec].values())
+        it_ms = sum(v["ms"] for v in kernels[prec].values())
+        gbs = it_bytes / (it_ms * 1e-3) / 1e9
+        roofline["iteration"][prec] = dict(bytes=it_bytes, us=round(it_ms * 1e3, 2), achieved=round(gbs, 1),
+                                           frac=round(gbs / HBM_PEAK_GBS, 4))
 
     log("adaptive step size: mixed, t in [0, %g]" % (100 * cfg["ht"]))
     adaptive = adaptive_leg(ctx, rd, torch, cfg, u0)

@@ -106,7 +106,8 @@ typedef struct {
     double omega;            /* extrapolation coefficient (the paper uses 1, Sec. 3)         */
     int32_t precision;       /* rd_precision                                                 */
     int32_t init;            /* rd_init: U_0 = U^k (paper) or the pointwise reaction prox    */
-    double inner_rtol;       /* mixed only: inner solve stops at ||F~(e)|| <= inner_rtol ||r|| */
+    double inner_rtol;       /* mixed only: inner solve stops at ||F~(e)|| <= max(inner_rtol ||r||,
+                                tol / 2)                                                     */
 } rd_opts;
 
 typedef struct {

@@ -387,7 +387,9 @@ __device__ __forceinline__ void finalize(SlotRef s, const double *sumsq, const d
         st->outer_done = odone;
         st->done = odone;
         st->iters = 0;
-        st->inner_target = s.inner_rtol * res;
+        // the inner loop reduces the outer residual by inner_rtol, but need not go
+        // below half the step's tolerance: the next outer test then passes
+        st->inner_target = fmax(s.inner_rtol * res, 0.5 * s.tol);
         st->inner_best = res;
         st->inner_best_it = 0;
     }

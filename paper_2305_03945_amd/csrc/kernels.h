@@ -13,10 +13,17 @@
 //                norm, the forward row transform into S.
 // The stop decision for the row pass (Sec. 2.1 stopping criterion) is taken by
 // one extra workgroup of the next column pass, which reduces the partial sums
-// in a fixed order while the other workgroups transform; after the initial and
-// outer passes and at the end of a chunk of iterations, by k_finalize.
-// Every kernel first reads the slot's State and returns at once when the slot
-// is finished, so a host may enqueue more iterations than needed.
+// in a fixed order while the other workgroups transform; after the initial pass
+// and at the end of a chunk of iterations, by k_finalize.
+// Mixed precision (2-D): the row pass reads from the State which pass the step
+// needs.  While the inner FP32 loop runs it is the inner iteration's; once the
+// inner loop has stopped, the next row-pass launch makes the FP64 outer update
+// instead (U += e, r = F(U), forward transform of r) and the decision after it
+// is the outer one, which either ends the step or starts the next inner loop
+// on the spectrum of r.  So one fixed launch sequence serves every split of a
+// step into inner loops, and the host needs to predict only its total length.
+// Every kernel first reads the slot's State and returns at once when it has
+// nothing to do, so a host may enqueue more iterations than needed.
 #pragma once
 #include "fft16.h"
 
@@ -28,7 +35,9 @@ enum {
     K_ITER64 = 1,     // FP64 path: W_{n+1} = F(U_{n+1})
     K_INNER32 = 2,    // mixed: W = F~(e_{n+1}) in FP32
     K_OUTER_INIT = 3, // mixed: U from u_n, r = F(U) in FP64, inner loop starts
-    K_OUTER_UPD = 4   // mixed: U += e (FP64), r = F(U) in FP64, next inner loop
+    K_OUTER_UPD = 4,  // mixed: U += e (FP64), r = F(U) in FP64, next inner loop
+    K_MIXED = 5       // mixed iteration pass: K_INNER32 while the inner loop runs,
+                      // K_OUTER_UPD once it has stopped (read from the State)
 };
 
 // ---------------------------------------------------------------- pointwise reaction prox
@@ -308,6 +317,13 @@ __device__ __forceinline__ bool finite_(double x) { return x == x && x - x == 0.
 // Slot stop decision after a residual reduction (thread 0 of the last workgroup).
 template <int KIND, int C>
 __device__ __forceinline__ void finalize(SlotRef s, const double *sumsq, const double *mass) {
+    if constexpr (KIND == K_MIXED) {
+        // the row pass being decided made the outer update iff the inner loop had
+        // stopped when it started; the State has not changed since
+        if (state_of(s).done) finalize<K_OUTER_UPD, C>(s, sumsq, mass);
+        else finalize<K_INNER32, C>(s, sumsq, mass);
+        return;
+    }
     State *st = s.st;
     double res = 0.0, m = 0.0;
 #pragma unroll
@@ -413,6 +429,7 @@ __device__ __forceinline__ void write_partials(SlotRef s, int tile, double *acc 
 template <int KIND> __device__ __forceinline__ bool skip_launch(StateRef sst) {
     if constexpr (KIND == K_INIT64 || KIND == K_OUTER_INIT) return false;
     else if constexpr (KIND == K_OUTER_UPD) return sst.outer_done || !sst.done;
+    else if constexpr (KIND == K_MIXED) return sst.outer_done != 0;
     else return sst.done != 0;
 }
 
@@ -851,17 +868,11 @@ __device__ __forceinline__ void rows_load_pre(cplx<T> *buf, const cplx<T> *S, in
 
 // ---------------------------------------------------------------- row pass, forward
 template <typename T, int LOGN, int BC, int EQ, int KIND>
-__global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
+__device__ __forceinline__ void row_forward_pass(SlotRef s, StateRef sst, cplx<T> *buf, double *scratch) {
     constexpr int N = 1 << LOGN, H = N / 2;
     constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
     constexpr int R = rows_per_block<T, LOGN, C>();
     constexpr int NREG = C * R / 2;
-    __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
-    __shared__ double scratch[2 * C * (NT / 64)];
-    SlotRef s = slot_of(slots);
-    StateRef sst = state_of(s);
-    if (skip_launch<KIND>(sst)) return;
-
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int y0 = tile * R;
     Tw16<T, LOGN> twr;
@@ -933,6 +944,23 @@ __global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
     }
     }
     write_partials<C>(s, tile, acc, scratch);
+}
+
+template <typename T, int LOGN, int BC, int EQ, int KIND>
+__global__ __launch_bounds__(NT) void k_row_forward(Slot *const *slots) {
+    constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
+    constexpr int NREG = C * rows_per_block<T, LOGN, C>() / 2;
+    __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
+    __shared__ double scratch[2 * C * (NT / 64)];
+    SlotRef s = slot_of(slots);
+    StateRef sst = state_of(s);
+    if (skip_launch<KIND>(sst)) return;
+    if constexpr (KIND == K_MIXED) {
+        if (sst.done) row_forward_pass<T, LOGN, BC, EQ, K_OUTER_UPD>(s, sst, buf, scratch);
+        else row_forward_pass<T, LOGN, BC, EQ, K_INNER32>(s, sst, buf, scratch);
+    } else {
+        row_forward_pass<T, LOGN, BC, EQ, KIND>(s, sst, buf, scratch);
+    }
 }
 
 // ---------------------------------------------------------------- column pass
@@ -1077,7 +1105,10 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>()), (col_waves_per_eu<T, L
             return;
         }
     }
-    if (skip_launch<K_ITER64>(sst)) return;
+    // A column pass transforms unless the step is finished: in the mixed path a
+    // pass that starts after the outer update is the first iteration of the next
+    // inner loop (outer_done equals done in the FP64 path).
+    if (sst.outer_done) return;
     // blockIdx.x -> (component, first column); CB divides N/2
     const int bx = xcd_tile(blockIdx.x, C * (H / CB));
     const int c = bx / (H / CB);

@@ -104,11 +104,12 @@ template <int BC, int EQ> void fill() {
 template <int BC, int EQ> void fill_mixed() {
     KSet &m = g_kernels[MODE_MIXED][L][BC][EQ];
     m.init = launch_rowfwd_fin<float, BC, EQ, K_OUTER_INIT>;
-    m.outer = launch_rowfwd_fin<float, BC, EQ, K_OUTER_UPD>;
-    m.rowfwd = launch_rowfwd<float, BC, EQ, K_INNER32>;
-    m.fin = launch_fin<K_INNER32, EQ>;
+    // the iteration row pass makes the outer update itself when the inner loop
+    // has stopped, and the decisions after it follow (no separate outer launch)
+    m.rowfwd = launch_rowfwd<float, BC, EQ, K_MIXED>;
+    m.fin = launch_fin<K_MIXED, EQ>;
     m.cols = launch_cols<float, BC, EQ, FIN_NONE>;
-    m.cols_fin = launch_cols<float, BC, EQ, K_INNER32>;
+    m.cols_fin = launch_cols<float, BC, EQ, K_MIXED>;
     m.rowinv = launch_rowinv<float, BC, EQ>;
     m.upd = launch_upd<float, BC, EQ, MODE_MIXED>;
     m.tin = launch_tin<float, BC, EQ>;

@@ -20,8 +20,8 @@ struct KSet {
     launch_fn fin = nullptr;        // stop decision of an iteration row pass (k_finalize)
     launch_fn rowinv = nullptr;     // inverse rows + dual update (T)
     launch_fn upd = nullptr;        // primal update (T)
-    launch_fn rowfwd = nullptr;     // FP64: K_ITER64; mixed: K_INNER32 (no decision)
-    launch_fn outer = nullptr;      // mixed: K_OUTER_UPD
+    launch_fn rowfwd = nullptr;     // FP64: K_ITER64; mixed: K_MIXED (2-D), K_INNER32 (3-D); no decision
+    launch_fn outer = nullptr;      // mixed 3-D: K_OUTER_UPD and its decision (2-D: in rowfwd)
     launch_fn yfwd = nullptr;       // 3-D: forward y-transforms
     launch_fn yfwd_fin = nullptr;   // 3-D: the same, plus the stop decision of the preceding row pass
     launch_fn zsym = nullptr;       // 3-D: forward z-transform, symbol, inverse z-transform

@@ -134,8 +134,31 @@ struct Workspace {
     Slot *slot_host = nullptr;    // pinned staging
     State *st_host = nullptr;     // pinned readback
     Slot proto{};                 // pointers filled at allocation
-    int last_iters = 0, last_outer = 0, last_inner = 0;
+    // the previous step on this workspace: FP64 iterations; mixed outer passes,
+    // mean inner iterations per pass, and (2-D) iteration launches it used
+    int last_iters = 0, last_outer = 0, last_inner = 0, last_slots = 0;
 };
+
+// Record the shape of a finished step for the next step's schedule.  A 2-D mixed
+// step uses one iteration launch per inner iteration and one per outer update.
+void remember_step(Workspace &w, const State &s) {
+    if (w.mode == MODE_F64) {
+        w.last_iters = s.iters;
+    } else {
+        w.last_outer = std::max(1, s.outer);
+        w.last_inner = s.outer > 0 ? std::max(1, (s.total_iters + s.outer - 1) / s.outer) : 6;
+        w.last_slots = s.total_iters + s.outer;
+    }
+}
+
+// Iterations the first chunk of a step enqueues: what the previous step used
+// and one more (FP64 and 2-D mixed), or the inner iterations of one pass (3-D
+// mixed, whose chunks hold `passes` inner loops, each with its outer pass).
+int first_chunk(const Workspace &w) {
+    if (w.mode == MODE_F64) return w.last_iters > 0 ? w.last_iters + 1 : 8;
+    if (w.dim == 2) return w.last_slots > 0 ? w.last_slots + 1 : 16;
+    return w.last_inner > 0 ? w.last_inner + 1 : 6;
+}
 
 // pts: points per component (N^2 or N^3)
 size_t field_bytes(size_t pts, int C, size_t elem) { return (size_t)C * pts * elem; }
@@ -401,16 +424,18 @@ void bind_workspace(Slot &s, const Workspace &w, const Tables &t) {
 
 // Launch schedule of one step, or of a batch of running slots of one key.
 // `slots`: device array of nslots Slot pointers.  Each call enqueues `iters`
-// PDHG iterations (FP64), or `passes` rounds of `iters` inner iterations each
-// followed by an outer FP64 pass (mixed).  Finished slots turn them into no-ops.
-// One chunk of iterations.  Every chunk starts after a decided row pass (the
-// initial or outer pass with its k_finalize, or the previous chunk's final
-// k_finalize); inside it, each column pass takes the decision of the row pass
-// before it, and the chunk (or the inner loop before an outer pass) ends with a
-// k_finalize so that the host and the outer pass see a decided State.
+// PDHG iterations (FP64, and 2-D mixed, whose row pass makes the outer update
+// itself when the inner loop has stopped), or, 3-D mixed, `passes` rounds of
+// `iters` inner iterations each followed by an outer FP64 pass.  Finished slots
+// turn them into no-ops.
+// Every chunk starts after a decided row pass (the initial pass with its
+// k_finalize, or the previous chunk's final k_finalize); inside it, each column
+// pass (3-D: forward y pass) takes the decision of the row pass before it, and
+// the chunk (3-D mixed: each inner loop before its outer pass) ends with a
+// k_finalize so that the host (and the outer pass) see a decided State.
 void enqueue_round(const KSet &k, int mode, Slot *const *slots, int nslots, int iters, int passes, hipStream_t st) {
-    const int np = mode == MODE_F64 ? 1 : passes;
     if (k.dim == 3) {
+        const int np = mode == MODE_F64 ? 1 : passes;
         // 3-D: the forward y pass takes the decision of the preceding row pass
         for (int p = 0; p < np; ++p) {
             for (int i = 0; i < iters; ++i) {
@@ -426,16 +451,13 @@ void enqueue_round(const KSet &k, int mode, Slot *const *slots, int nslots, int 
         }
         return;
     }
-    for (int p = 0; p < np; ++p) {
-        for (int i = 0; i < iters; ++i) {
-            (i == 0 ? k.cols : k.cols_fin)(slots, nslots, st, nullptr);
-            k.rowinv(slots, nslots, st, nullptr);
-            k.upd(slots, nslots, st, nullptr);
-            k.rowfwd(slots, nslots, st, nullptr);
-        }
-        k.fin(slots, nslots, st, nullptr);
-        if (mode == MODE_MIXED) k.outer(slots, nslots, st, nullptr);
+    for (int i = 0; i < iters; ++i) {
+        (i == 0 ? k.cols : k.cols_fin)(slots, nslots, st, nullptr);
+        k.rowinv(slots, nslots, st, nullptr);
+        k.upd(slots, nslots, st, nullptr);
+        k.rowfwd(slots, nslots, st, nullptr);
     }
+    k.fin(slots, nslots, st, nullptr);
 }
 
 void info_from_state(const State &s, int mode, rd_info *info) {
@@ -480,10 +502,12 @@ rd_status run_step(Ctx *c, Workspace &w, const KSet &k, hipStream_t st, int max_
     while (true) {
         int iters, passes = 1;
         if (w.mode == MODE_F64) {
-            iters = rounds == 0 ? (w.last_iters > 0 ? w.last_iters + 1 : 8) : std::max(4, issued / 4);
+            iters = rounds == 0 ? first_chunk(w) : std::max(4, issued / 4);
             if (max_iter - issued + 1 < iters) iters = std::max(1, max_iter - issued + 1);
+        } else if (w.dim == 2) {
+            iters = rounds == 0 ? first_chunk(w) : std::max(4, issued / 4);
         } else {
-            iters = rounds == 0 ? (w.last_inner > 0 ? w.last_inner + 1 : 6) : std::max(3, w.last_inner);
+            iters = rounds == 0 ? first_chunk(w) : std::max(3, w.last_inner);
             passes = rounds == 0 ? (w.last_outer > 0 ? w.last_outer : 3) : 1;
         }
         enqueue_round(k, w.mode, slots, 1, iters, passes, st);
@@ -498,16 +522,10 @@ rd_status run_step(Ctx *c, Workspace &w, const KSet &k, hipStream_t st, int max_
         // The device enforces max_iter / max_outer; this bound only guards
         // against a host-side schedule that never reaches them.
         const long cap = w.mode == MODE_F64 ? (long)max_iter + 8
-                                            : (long)(max_outer + 1) * (long)(max_iter + 1) + 16;
+                                            : (long)(max_outer + 1) * (long)(max_iter + 2) + 16;
         if (issued > cap + 64) return RD_E_DEVICE;
     }
-    const State &s = *w.st_host;
-    if (w.mode == MODE_F64) {
-        w.last_iters = s.iters;
-    } else {
-        w.last_outer = std::max(1, s.outer);
-        w.last_inner = s.outer > 0 ? std::max(1, (s.total_iters + s.outer - 1) / s.outer) : 6;
-    }
+    remember_step(w, *w.st_host);
     (void)c;
     return RD_OK;
 }
@@ -1094,9 +1112,7 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
         int iters = 0;
         for (Traj *t : kv.second) {
             const Workspace &w = *t->ws;
-            const int pred = key.mode == MODE_F64 ? (w.last_iters > 0 ? w.last_iters + 1 : 8)
-                                                  : (w.last_inner > 0 ? w.last_inner + 1 : 6);
-            iters = std::max(iters, std::max(pred, t->issued / 2));
+            iters = std::max(iters, std::max(first_chunk(w), t->issued / 2));
         }
         iters = std::min(iters, 64);
         for (Traj *t : kv.second) t->issued += iters;
@@ -1119,11 +1135,7 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
             Ticket &tk = c->tickets[t->running_ticket];
             info_from_state(s, w.mode, &tk.info);
             tk.done = true;
-            if (w.mode == MODE_F64) w.last_iters = s.iters;
-            else {
-                w.last_outer = std::max(1, s.outer);
-                w.last_inner = s.outer > 0 ? std::max(1, (s.total_iters + s.outer - 1) / s.outer) : 6;
-            }
+            remember_step(w, s);
             t->running = false;
         }
     }

@@ -28,6 +28,26 @@ void launch_residual(int bc, int eq, const Slot *slot_dev, int N, const double *
 #undef RD_RES
 }
 
+// Result of a finished step -> the caller's buffer (n doubles, n % 4 == 0): the
+// FP64 iterate U[iters & 1] or the mixed path's FP64 U64[outer & 1].  Returns at
+// once while the step still runs, so the host enqueues it after every chunk of
+// iterations and needs no launch of its own once the step has finished.
+__global__ __launch_bounds__(NT) void k_copy_out(Slot *const *slots, double *out, size_t n) {
+    SlotRef s = slot_of(slots);
+    StateRef sst = state_of(s);
+    if (!sst.outer_done) return;
+    const double *src = s.mode == MODE_F64 ? (const double *)s.U[sst.iters & 1] : s.U64[sst.outer & 1];
+    const auto in4 = gp((const vec4_t<double> *)src);
+    const auto out4 = gp((vec4_t<double> *)out);
+    for (size_t i = blockIdx.x * (size_t)NT + threadIdx.x; i < n / 4; i += (size_t)gridDim.x * NT) out4[i] = in4[i];
+}
+
+void launch_copy_out(Slot *const *slots, double *out, size_t n, hipStream_t st) {
+    const size_t want = (n / 4 + NT - 1) / NT;
+    const int blocks = (int)(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL(k_copy_out, dim3(blocks), dim3(NT), 0, st, slots, out, n);
+}
+
 void launch_prox(int eq, const Slot *slot_dev, int N, const double *c, double *u, hipStream_t st) {
     const int blocks = (int)(((size_t)N * N + NT - 1) / NT);
     if (eq == EQ_LAP5) hipLaunchKernelGGL((k_prox<EQ_LAP5>), dim3(blocks), dim3(NT), 0, st, slot_dev, c, u);

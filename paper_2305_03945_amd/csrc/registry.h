@@ -47,5 +47,8 @@ RD_DECLARE_LOGN(9) RD_DECLARE_LOGN(10) RD_DECLARE_LOGN(11) RD_DECLARE_LOGN(12)
 void launch_residual(int bc, int eq, const Slot *slot_dev, int N, const double *U, const double *Uk, double *W,
                      double *partials, hipStream_t st);
 void launch_prox(int eq, const Slot *slot_dev, int N, const double *c, double *u, hipStream_t st);
+// Copy of a finished step's result (n doubles, n % 4 == 0) to out; a no-op while
+// the slot's step runs.
+void launch_copy_out(Slot *const *slots, double *out, size_t n, hipStream_t st);
 
 }  // namespace rdk

@@ -205,6 +205,28 @@ def test_in_place_step_equals_out_of_place(ctx, rd, precision, dim):
     assert np.array_equal(u.cpu().numpy(), ref.cpu().numpy())
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_unaligned_output_buffer(ctx, rd, precision):
+    """The result reaches an output buffer at any 8-byte offset (the device-side copy
+    needs 32-byte alignment; other buffers take the host-enqueued copy): bitwise the
+    aligned result, and the doubles around the output are untouched."""
+    import torch
+    N = 64
+    cfg = small_cfg("allen_cahn", N, "periodic")
+    U0 = wl.uniform_field(N, -0.5, 0.5, 15)
+    p = rd.problem_from_config(cfg)
+    o = gpu_opts(rd, cfg, precision, tol=1e-8)
+    ref, i_ref = ctx.step(dev(U0), cfg["ht"], p, o)
+    for off in (1, 2, 3, 4):
+        big = torch.full((N * N + 8,), 7.0, dtype=torch.float64, device="cuda")
+        out = big[off:off + N * N].view(N, N)
+        _, info = ctx.step(dev(U0), cfg["ht"], p, o, out=out)
+        assert info["iters"] == i_ref["iters"] and info["status"] == "ok"
+        assert np.array_equal(out.cpu().numpy(), ref.cpu().numpy()), off
+        rest = torch.cat([big[:off], big[off + N * N:]]).cpu().numpy()
+        assert np.all(rest == 7.0), off
+
+
 def test_invalid_problems_rejected_before_any_device_work(ctx, rd):
     """Shapes and operator/reaction pairs the library does not take: rd_footprint_bytes
     is 0 and rd_step returns RD_E_INVALID, without touching the (one-value) buffers."""

@@ -8,7 +8,8 @@
 // One iteration is six launches:
 //   k3_rowinv      inverse x-transforms of Y -> P_{n+1}, P~ (eqs. 21-22)
 //   k3_upd         U_{n+1} = U_n - tau_u grad F(U_n)^T P~ (eq. 23)
-//   k3_row_forward W = F(U_{n+1}) (or F~(e)), partial norms, forward x-transforms
+//   k3_row_forward W = F(U_{n+1}) (or F~(e), or the mixed outer update), partial
+//                  norms, forward x-transforms
 //   k3_lines YFWD  forward y-transforms of the x-spectra; one extra workgroup
 //                  takes the stop decision of the preceding row pass
 //   k3_lines ZSYM  forward z-transform, multiply by 1 / (N^3 g), inverse z-transform
@@ -256,16 +257,11 @@ template <int LOGN> __device__ __forceinline__ size_t s3_off(int c, int z, int y
 // ---------------------------------------------------------------- x-pass, forward
 // Workgroup = R consecutive rows (z, y0 .. y0+R-1) of every component.
 template <typename T, int LOGN, int BC, int EQ, int KIND>
-__global__ __launch_bounds__(NT) void k3_row_forward(Slot *const *slots) {
+__device__ __forceinline__ void row3_forward_pass(SlotRef s, StateRef sst, cplx<T> *buf, double *scratch) {
     constexpr int N = 1 << LOGN, H = N / 2;
     constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
     constexpr int R = rows_per_block<T, LOGN, C>();
     constexpr int NREG = C * R / 2;
-    __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
-    __shared__ double scratch[2 * C * (NT / 64)];
-    SlotRef s = slot_of(slots);
-    StateRef sst = state_of(s);
-    if (skip_launch<KIND>(sst)) return;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int z = tile / (N / R), y0 = (tile % (N / R)) * R;
     Tw16<T, LOGN> twr;
@@ -295,6 +291,25 @@ __global__ __launch_bounds__(NT) void k3_row_forward(Slot *const *slots) {
         S[s3_off<LOGN>(c, z, y0 + r, j)] = buf[rix<LOGN>(c * R / 2 + r / 2, (r & 1) * H + j)];
     }
     write_partials<C>(s, tile, acc, scratch);
+}
+
+// KIND K_MIXED: the inner FP32 pass or, once the inner loop has stopped, the FP64
+// outer update, read from the State (as the 2-D row pass).
+template <typename T, int LOGN, int BC, int EQ, int KIND>
+__global__ __launch_bounds__(NT) void k3_row_forward(Slot *const *slots) {
+    constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
+    constexpr int NREG = C * rows_per_block<T, LOGN, C>() / 2;
+    __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
+    __shared__ double scratch[2 * C * (NT / 64)];
+    SlotRef s = slot_of(slots);
+    StateRef sst = state_of(s);
+    if (skip_launch<KIND>(sst)) return;
+    if constexpr (KIND == K_MIXED) {
+        if (sst.done) row3_forward_pass<T, LOGN, BC, EQ, K_OUTER_UPD>(s, sst, buf, scratch);
+        else row3_forward_pass<T, LOGN, BC, EQ, K_INNER32>(s, sst, buf, scratch);
+    } else {
+        row3_forward_pass<T, LOGN, BC, EQ, KIND>(s, sst, buf, scratch);
+    }
 }
 
 // ---------------------------------------------------------------- x-pass, inverse + dual update
@@ -600,7 +615,10 @@ __global__ __launch_bounds__((line_threads<T, LOGN>())) void k3_lines(Slot *cons
             return;
         }
     }
-    if (skip_launch<K_ITER64>(sst)) return;
+    // The forward y pass transforms unless the step is finished (after a mixed
+    // outer update it is the first iteration of the next inner loop, while its
+    // decision workgroup runs); the later line passes see a decided State.
+    if (PASS == L3_YFWD ? sst.outer_done != 0 : sst.done != 0) return;
     // blockIdx.x -> (component, plane or row, first slot); CB divides N/2
     // 256^3: consecutive blocks (adjacent slot groups, then lines) on one XCD
     // (FP64 line passes 20-25 % faster there; at 128^3 the round-robin order is

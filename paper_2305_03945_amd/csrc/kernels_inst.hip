@@ -37,7 +37,7 @@ void launch_fin(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) 
                           ev_stop(ev), 0, slots);
 }
 
-// Initial and outer passes: row kernel, then its decision at once.
+// Initial pass: row kernel, then its decision at once.
 template <typename T, int BC, int EQ, int KIND>
 void launch_rowfwd_fin(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
     hipEvent_t e0[2] = {ev_start(ev), nullptr}, e1[2] = {nullptr, ev_stop(ev)};
@@ -181,11 +181,11 @@ void launch3_tout(Slot *const *slots, int nslots, const double *, double *out, h
 
 template <typename T, int BC, int EQ, int MODE> void fill3_mode(KSet &k) {
     constexpr bool f64 = MODE == MODE_F64;
-    constexpr int KIT = f64 ? K_ITER64 : K_INNER32;
+    // mixed: the row pass makes the outer update itself (as in 2-D)
+    constexpr int KIT = f64 ? K_ITER64 : K_MIXED;
     k.init = launch3_rowfwd_fin<T, BC, EQ, f64 ? K_INIT64 : K_OUTER_INIT>;
     k.rowfwd = launch3_rowfwd<T, BC, EQ, KIT>;
     k.fin = launch_fin<KIT, EQ>;
-    if constexpr (!f64) k.outer = launch3_rowfwd_fin<T, BC, EQ, K_OUTER_UPD>;
     k.yfwd = launch3_lines<T, BC, EQ, L3_YFWD, FIN_NONE>;
     k.yfwd_fin = launch3_lines<T, BC, EQ, L3_YFWD, KIT>;
     k.zsym = launch3_lines<T, BC, EQ, L3_ZSYM, FIN_NONE>;

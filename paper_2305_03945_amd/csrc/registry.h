@@ -20,8 +20,7 @@ struct KSet {
     launch_fn fin = nullptr;        // stop decision of an iteration row pass (k_finalize)
     launch_fn rowinv = nullptr;     // inverse rows + dual update (T)
     launch_fn upd = nullptr;        // primal update (T)
-    launch_fn rowfwd = nullptr;     // FP64: K_ITER64; mixed: K_MIXED (2-D), K_INNER32 (3-D); no decision
-    launch_fn outer = nullptr;      // mixed 3-D: K_OUTER_UPD and its decision (2-D: in rowfwd)
+    launch_fn rowfwd = nullptr;     // FP64: K_ITER64; mixed: K_MIXED (inner or outer pass); no decision
     launch_fn yfwd = nullptr;       // 3-D: forward y-transforms
     launch_fn yfwd_fin = nullptr;   // 3-D: the same, plus the stop decision of the preceding row pass
     launch_fn zsym = nullptr;       // 3-D: forward z-transform, symbol, inverse z-transform
@@ -29,7 +28,7 @@ struct KSet {
     launch_io_fn tin = nullptr;     // precond-only: FP64 W -> row transforms into S
     launch_io_fn tout = nullptr;    // precond-only: S -> inverse rows -> FP64 Y
     int rows_per_block = 0;
-    int dim = 2;                    // 3: the 3-D launch sequence (row passes carry the decision)
+    int dim = 2;                    // 3: the 3-D launch sequence (line passes between the row passes)
 };
 
 constexpr int LOGN_MIN = 4, LOGN_MAX = 12;

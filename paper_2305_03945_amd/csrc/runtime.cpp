@@ -134,30 +134,23 @@ struct Workspace {
     Slot *slot_host = nullptr;    // pinned staging
     State *st_host = nullptr;     // pinned readback
     Slot proto{};                 // pointers filled at allocation
-    // the previous step on this workspace: FP64 iterations; mixed outer passes,
-    // mean inner iterations per pass, and (2-D) iteration launches it used
-    int last_iters = 0, last_outer = 0, last_inner = 0, last_slots = 0;
+    // iteration launches the previous step on this workspace used (FP64: its
+    // iterations; mixed: its inner iterations plus one per outer update)
+    int last_iters = 0;
 };
 
-// Record the shape of a finished step for the next step's schedule.  A 2-D mixed
-// step uses one iteration launch per inner iteration and one per outer update.
+// Record the length of a finished step for the next step's schedule.  A mixed
+// step uses one iteration launch per inner iteration and one per outer update
+// (the row pass of that launch makes the update).
 void remember_step(Workspace &w, const State &s) {
-    if (w.mode == MODE_F64) {
-        w.last_iters = s.iters;
-    } else {
-        w.last_outer = std::max(1, s.outer);
-        w.last_inner = s.outer > 0 ? std::max(1, (s.total_iters + s.outer - 1) / s.outer) : 6;
-        w.last_slots = s.total_iters + s.outer;
-    }
+    w.last_iters = w.mode == MODE_F64 ? s.iters : s.total_iters + s.outer;
 }
 
-// Iterations the first chunk of a step enqueues: what the previous step used
-// and one more (FP64 and 2-D mixed), or the inner iterations of one pass (3-D
-// mixed, whose chunks hold `passes` inner loops, each with its outer pass).
+// Iterations the first chunk of a step enqueues: what the previous step used,
+// and one more.
 int first_chunk(const Workspace &w) {
-    if (w.mode == MODE_F64) return w.last_iters > 0 ? w.last_iters + 1 : 8;
-    if (w.dim == 2) return w.last_slots > 0 ? w.last_slots + 1 : 16;
-    return w.last_inner > 0 ? w.last_inner + 1 : 6;
+    if (w.last_iters > 0) return w.last_iters + 1;
+    return w.mode == MODE_F64 ? 8 : 16;
 }
 
 // pts: points per component (N^2 or N^3)
@@ -423,32 +416,25 @@ void bind_workspace(Slot &s, const Workspace &w, const Tables &t) {
 }
 
 // Launch schedule of one step, or of a batch of running slots of one key.
-// `slots`: device array of nslots Slot pointers.  Each call enqueues `iters`
-// PDHG iterations (FP64, and 2-D mixed, whose row pass makes the outer update
-// itself when the inner loop has stopped), or, 3-D mixed, `passes` rounds of
-// `iters` inner iterations each followed by an outer FP64 pass.  Finished slots
-// turn them into no-ops.
-// Every chunk starts after a decided row pass (the initial pass with its
-// k_finalize, or the previous chunk's final k_finalize); inside it, each column
-// pass (3-D: forward y pass) takes the decision of the row pass before it, and
-// the chunk (3-D mixed: each inner loop before its outer pass) ends with a
-// k_finalize so that the host (and the outer pass) see a decided State.
-void enqueue_round(const KSet &k, int mode, Slot *const *slots, int nslots, int iters, int passes, hipStream_t st) {
+// `slots`: device array of nslots Slot pointers.  Each call enqueues one chunk
+// of `iters` iterations: PDHG iterations (FP64), or mixed iterations whose row
+// pass makes the FP64 outer update instead when the inner loop has stopped.
+// Finished slots turn them into no-ops.  Every chunk starts after a decided row
+// pass (the initial pass with its k_finalize, or the previous chunk's final
+// k_finalize); inside it, each column pass (3-D: forward y pass) takes the
+// decision of the row pass before it, and the chunk ends with a k_finalize so
+// that the host sees a decided State.
+void enqueue_round(const KSet &k, Slot *const *slots, int nslots, int iters, hipStream_t st) {
     if (k.dim == 3) {
-        const int np = mode == MODE_F64 ? 1 : passes;
-        // 3-D: the forward y pass takes the decision of the preceding row pass
-        for (int p = 0; p < np; ++p) {
-            for (int i = 0; i < iters; ++i) {
-                (i == 0 ? k.yfwd : k.yfwd_fin)(slots, nslots, st, nullptr);
-                k.zsym(slots, nslots, st, nullptr);
-                k.yinv(slots, nslots, st, nullptr);
-                k.rowinv(slots, nslots, st, nullptr);
-                k.upd(slots, nslots, st, nullptr);
-                k.rowfwd(slots, nslots, st, nullptr);
-            }
-            k.fin(slots, nslots, st, nullptr);
-            if (mode == MODE_MIXED) k.outer(slots, nslots, st, nullptr);
+        for (int i = 0; i < iters; ++i) {
+            (i == 0 ? k.yfwd : k.yfwd_fin)(slots, nslots, st, nullptr);
+            k.zsym(slots, nslots, st, nullptr);
+            k.yinv(slots, nslots, st, nullptr);
+            k.rowinv(slots, nslots, st, nullptr);
+            k.upd(slots, nslots, st, nullptr);
+            k.rowfwd(slots, nslots, st, nullptr);
         }
+        k.fin(slots, nslots, st, nullptr);
         return;
     }
     for (int i = 0; i < iters; ++i) {
@@ -504,20 +490,12 @@ rd_status run_step(Ctx *c, Workspace &w, const KSet &k, hipStream_t st, int max_
     RD_CHECK(hipGetLastError());
     int issued = 0, rounds = 0;
     while (true) {
-        int iters, passes = 1;
-        if (w.mode == MODE_F64) {
-            iters = rounds == 0 ? first_chunk(w) : std::max(4, issued / 4);
-            if (max_iter - issued + 1 < iters) iters = std::max(1, max_iter - issued + 1);
-        } else if (w.dim == 2) {
-            iters = rounds == 0 ? first_chunk(w) : std::max(4, issued / 4);
-        } else {
-            iters = rounds == 0 ? first_chunk(w) : std::max(3, w.last_inner);
-            passes = rounds == 0 ? (w.last_outer > 0 ? w.last_outer : 3) : 1;
-        }
-        enqueue_round(k, w.mode, slots, 1, iters, passes, st);
+        int iters = rounds == 0 ? first_chunk(w) : std::max(4, issued / 4);
+        if (w.mode == MODE_F64 && max_iter - issued + 1 < iters) iters = std::max(1, max_iter - issued + 1);
+        enqueue_round(k, slots, 1, iters, st);
         if (out) launch_copy_out(slots, out, nout, st);
         RD_CHECK(hipGetLastError());
-        issued += iters * passes;
+        issued += iters;
         ++rounds;
         RD_CHECK(hipMemcpyAsync(w.st_host, w.proto.st, sizeof(State), hipMemcpyDeviceToHost, st));
         RD_CHECK(hipStreamSynchronize(st));
@@ -1127,7 +1105,7 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
         }
         iters = std::min(iters, 64);
         for (Traj *t : kv.second) t->issued += iters;
-        enqueue_round(k, key.mode, dev, (int)kv.second.size(), iters, 1, st);
+        enqueue_round(k, dev, (int)kv.second.size(), iters, st);
         RD_CHECK(hipGetLastError());
         for (Traj *t : kv.second)
             RD_CHECK(hipMemcpyAsync(t->ws->st_host, t->ws->proto.st, sizeof(State), hipMemcpyDeviceToHost, st));

@@ -366,14 +366,110 @@ __global__ __launch_bounds__(NT) void k3_rowinv(Slot *const *slots) {
 }
 
 // ---------------------------------------------------------------- primal update
+// z-planes one thread of the primal update walks (0: one set of four points per
+// thread).  Walking in z, the thread keeps P~ of planes z - 1, z, z + 1 at its
+// four points in registers, so each P~ value is read from memory once per pass
+// instead of three times (as the centre and as the z-neighbour of two planes);
+// the y- and x-neighbours are in the same plane and come from L1/L2.  It pays
+// where the z-neighbour planes of the workgroups resident on one XCD no longer
+// fit its L2: FP64 on 256^3 (131 -> 101 us per launch with 32 planes per
+// thread; 16: 109, 8: 114).  FP32 on 256^3 and both precisions on 128^3 measured
+// no gain or a loss, and keep one set of points per thread.
+template <typename T, int LOGN> constexpr int upd3_zb() { return (sizeof(T) == 8 && LOGN >= 8) ? 32 : 0; }
+template <typename T, int LOGN> constexpr int upd3_blocks() {
+    constexpr size_t N = (size_t)1 << LOGN;
+    return upd3_zb<T, LOGN>() == 0 ? (int)((N * N * N / 4 + NT - 1) / NT)
+                                   : (int)(N * N / (4 * NT) * (N / upd3_zb<T, LOGN>()));
+}
+
 template <typename T, int LOGN, int BC, int EQ, int MODE>
 __global__ __launch_bounds__(NT) void k3_upd(Slot *const *slots) {
     constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
     constexpr int N = 1 << LOGN;
     constexpr size_t NN = (size_t)N * N * N;
+    constexpr size_t PL = (size_t)N * N;
+    constexpr int ZB = upd3_zb<T, LOGN>();
     SlotRef s = slot_of(slots);
     StateRef sst = state_of(s);
     if (skip_launch<K_ITER64>(sst)) return;
+    if constexpr (ZB > 0) {
+        // workgroup -> (block of ZB planes, tile of 4 NT points of a plane);
+        // consecutive workgroups (one XCD) take adjacent tiles of the same planes
+        constexpr int TPP = (int)(PL / (4 * NT));
+        const int b = xcd_tile(blockIdx.x, gridDim.x);
+        const int z0 = (b / TPP) * ZB;
+        const size_t off = ((size_t)(b % TPP) * NT + threadIdx.x) * 4;   // in-plane
+        const int x0 = (int)(off & (N - 1)), y = (int)(off >> LOGN);
+        const size_t rowm = (size_t)wrap<BC>(y - 1, N) * N + x0, rowp = (size_t)wrap<BC>(y + 1, N) * N + x0;
+        const size_t xl = (size_t)y * N + wrap<BC>(x0 - 1, N), xr = (size_t)y * N + wrap<BC>(x0 + 4, N);
+        const int it = sst.iters;
+        const auto Pt = gp((const T *)s.Pt);
+        const auto Ucur = gp((const T *)s.U[it & 1]);
+        const auto Unext = gp((T *)s.U[(it + 1) & 1]);
+        const auto Ub = gp((const float *)s.Ub32);
+        const T tu = (T)s.tau_u;
+        vec4_t<T> pm[C], pc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            pm[c] = load4<T>(Pt + c * NN + (size_t)wrap<BC>(z0 - 1, N) * PL + off);
+            pc[c] = load4<T>(Pt + c * NN + (size_t)z0 * PL + off);
+        }
+#pragma unroll 2
+        for (int j = 0; j < ZB; ++j) {
+            const int z = z0 + j;
+            const size_t pz = (size_t)z * PL;
+            Win3<T> wp[C];
+            vec4_t<T> pn[C], un[C];
+            T Uc[4][C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const auto P = Pt + c * NN;
+                pn[c] = load4<T>(P + (size_t)wrap<BC>(z + 1, N) * PL + off);
+                wp[c].c[0] = P[pz + xl];
+                wp[c].c[5] = P[pz + xr];
+                const vec4_t<T> ym = load4<T>(P + pz + rowm), yp = load4<T>(P + pz + rowp);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    wp[c].c[1 + k] = pc[c][k];
+                    wp[c].r[0][k] = ym[k];
+                    wp[c].r[1][k] = yp[k];
+                    wp[c].r[2][k] = pm[c][k];
+                    wp[c].r[3][k] = pn[c][k];
+                }
+                if constexpr (MODE == MODE_F64) {
+                    un[c] = load4<T>(Ucur + c * NN + pz + off);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) Uc[k][c] = un[c][k];
+                } else {
+                    if (it == 0) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) un[c][k] = (T)0;
+                    } else {
+                        un[c] = load4<T>(Ucur + c * NN + pz + off);
+                    }
+                    const vec4_t<float> ub = load4<float>(Ub + c * NN + pz + off);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) Uc[k][c] = (T)ub[k] + un[c][k];
+                }
+            }
+            vec4_t<T> out[C];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                T adj[C];
+                eval_adjoint3<EQ, T>(s, [&](int c, int dz, int dy, int dx) { return wp[c].at(k, dz, dy, dx); },
+                                     Uc[k], adj);
+#pragma unroll
+                for (int c = 0; c < C; ++c) out[c][k] = un[c][k] - tu * adj[c];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                store4<T>(Unext + c * NN + pz + off, out[c]);
+                pm[c] = pc[c];
+                pc[c] = pn[c];
+            }
+        }
+        return;
+    }
     const size_t g0 = ((size_t)xcd_tile(blockIdx.x, gridDim.x) * NT + threadIdx.x) * 4;
     if (g0 >= NN) return;
     const int x0 = (int)(g0 & (N - 1)), y = (int)((g0 >> LOGN) & (N - 1)), z = (int)(g0 >> (2 * LOGN));

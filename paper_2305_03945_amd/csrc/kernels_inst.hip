@@ -157,10 +157,8 @@ void launch3_rowinv(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *
 
 template <typename T, int BC, int EQ, int MODE>
 void launch3_upd(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
-    constexpr size_t N = (size_t)1 << L;
-    constexpr int blocks = (int)((N * N * N / 4 + NT - 1) / NT);
-    hipExtLaunchKernelGGL((k3_upd<T, L, BC, EQ, MODE>), dim3(blocks, nslots), dim3(NT), 0, st, ev_start(ev),
-                          ev_stop(ev), 0, slots);
+    hipExtLaunchKernelGGL((k3_upd<T, L, BC, EQ, MODE>), dim3(upd3_blocks<T, L>(), nslots), dim3(NT), 0, st,
+                          ev_start(ev), ev_stop(ev), 0, slots);
 }
 
 template <typename T, int BC, int EQ>

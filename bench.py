@@ -58,7 +58,7 @@ def counted_traffic(prec, kernel, logn):
     if d.get("source_hash") != profsum.source_hash():
         return None
     t = "float" if prec == "mixed" else "double"
-    kind = {"mixed": 2, "fp64": 1}[prec]
+    kind = {"mixed": 5, "fp64": 1}[prec]   # 5: the mixed row pass (its inner launches)
     names = {"cols": "k_cols<%s,%d,0,1,%d>" % (t, logn, kind), "rowinv": "k_rowinv<%s,%d,0,1>" % (t, logn),
              "upd": "k_upd<%s,%d,0,0,%d>" % (t, logn, 1 if prec == "mixed" else 0),
              "rowfwd": "k_row_forward<%s,%d,0,0,%d>" % (t, logn, kind)}

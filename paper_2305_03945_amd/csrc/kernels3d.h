@@ -368,13 +368,14 @@ __global__ __launch_bounds__(NT) void k3_rowinv(Slot *const *slots) {
 // ---------------------------------------------------------------- primal update
 // z-planes one thread of the primal update walks (0: one set of four points per
 // thread).  Walking in z, the thread keeps P~ of planes z - 1, z, z + 1 at its
-// four points in registers, so each P~ value is read from memory once per pass
-// instead of three times (as the centre and as the z-neighbour of two planes);
-// the y- and x-neighbours are in the same plane and come from L1/L2.  It pays
-// where the z-neighbour planes of the workgroups resident on one XCD no longer
-// fit its L2: FP64 on 256^3 (131 -> 101 us per launch with 32 planes per
-// thread; 16: 109, 8: 114).  FP32 on 256^3 and both precisions on 128^3 measured
-// no gain or a loss, and keep one set of points per thread.
+// four points in registers, so its z-neighbours need no load: per set of four
+// points the thread requests P~ from the caches three times (centre row and
+// the rows y - 1, y + 1) instead of five.  The HBM bytes stay the same (the
+// counters read 412 MB per launch either way, 403 MB algorithmic); what drops
+// is the number of requests the CUs send to L2, and the FP64 update on 256^3
+// runs 131 -> 101 us per launch with 32 planes per thread (16: 109, 8: 114).
+// FP32 on 256^3 and both precisions on 128^3 measured no gain or a loss, and
+// keep one set of points per thread.
 template <typename T, int LOGN> constexpr int upd3_zb() { return (sizeof(T) == 8 && LOGN >= 8) ? 32 : 0; }
 template <typename T, int LOGN> constexpr int upd3_blocks() {
     constexpr size_t N = (size_t)1 << LOGN;

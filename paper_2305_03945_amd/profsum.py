@@ -6,7 +6,10 @@
 ``trace`` reads ``<prefix>_kernel_trace.csv`` of a ``--kernel-trace --stats`` run
 and prints a per-kernel table.  Launches that found their slot finished return
 at once (the host enqueues iterations speculatively); the "working" columns
-keep only launches longer than half the kernel's median duration.
+keep only launches longer than half the kernel's median duration.  The mixed
+row pass (last template argument 5) makes either the FP32 inner iteration or,
+once an inner loop has stopped, the FP64 outer update: its launches above 1.6x
+the median (duration, or counter value) are listed apart as ``<kernel>:outer``.
 
 ``traffic`` reads the ``<prefix>_counter_collection.csv`` of two ``--pmc`` runs
 (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) and scales both by what the same
@@ -39,12 +42,28 @@ def _working(values):
     return [v for v in values if v >= 0.5 * med]
 
 
+MIXED_ROW = re.compile(r"row_forward<.*,5>$")
+
+
+def _split_outer(by):
+    """Move the outer-update launches of the mixed row pass to a key of their own.
+    by: kernel -> {launch id: value}."""
+    for k in [k for k in by if MIXED_ROW.search(k)]:
+        med = statistics.median(by[k].values())
+        outer = {i: v for i, v in by[k].items() if v > 1.6 * med}
+        if outer:
+            by[k + ":outer"] = outer
+            by[k] = {i: v for i, v in by[k].items() if v <= 1.6 * med}
+    return by
+
+
 def trace_table(path):
     rows = list(csv.DictReader(open(path)))
     by = {}
-    for r in rows:
+    for i, r in enumerate(rows):
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-        by.setdefault(short_name(r["Kernel_Name"]), []).append(d)
+        by.setdefault(short_name(r["Kernel_Name"]), {})[i] = d
+    by = {k: list(v.values()) for k, v in _split_outer(by).items()}
     out = []
     for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
         w = _working(v)
@@ -61,6 +80,7 @@ def counter_table(path, counter):
             continue
         by.setdefault(short_name(r["Kernel_Name"]), {}).setdefault(r["Dispatch_Id"], 0.0)
         by[short_name(r["Kernel_Name"])][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    by = _split_outer(by)
     out = {}
     for k, d in by.items():
         w = _working(list(d.values()))

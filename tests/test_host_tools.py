@@ -29,6 +29,23 @@ def test_trace_table_averages_and_drops_converged_launches(tmp_path):
     assert abs(t[0]["avg_us"] - 37.0 / 4) < 1e-9
 
 
+def test_trace_table_lists_the_outer_updates_of_the_mixed_row_pass_apart(tmp_path):
+    k = "void rdk::k_row_forward<float, 11, 0, 0, 5>(rdk::Slot* const*)"
+    # five inner launches of 16 us, two outer updates of 40 us, one early return
+    rows = [(k, 100000 * i, 100000 * i + 16000) for i in range(5)]
+    rows += [(k, 600000, 640000), (k, 700000, 740000), (k, 800000, 801000)]
+    _write_trace(tmp_path / "x_kernel_trace.csv", rows)
+    t = {r["kernel"]: r for r in profsum.trace_table(str(tmp_path / "x_kernel_trace.csv"))}
+    inner, outer = t["k_row_forward<float,11,0,0,5>"], t["k_row_forward<float,11,0,0,5>:outer"]
+    assert inner["calls"] == 6 and inner["working_calls"] == 5 and abs(inner["working_avg_us"] - 16.0) < 1e-9
+    assert outer["calls"] == 2 and abs(outer["working_avg_us"] - 40.0) < 1e-9
+    # other kernels keep their long launches
+    k2 = "void rdk::k_row_forward<double, 11, 0, 0, 1>(rdk::Slot* const*)"
+    _write_trace(tmp_path / "y_kernel_trace.csv", [(k2, 0, 10000), (k2, 20000, 30000), (k2, 40000, 70000)])
+    t2 = profsum.trace_table(str(tmp_path / "y_kernel_trace.csv"))
+    assert len(t2) == 1 and t2[0]["working_calls"] == 3
+
+
 def test_traffic_scaling_by_the_calibration_copy(tmp_path):
     k = "void rdk::k_upd<float, 11, 0, 0, 1>(rdk::Slot* const*)"
     cal = "void at::native::neg_kernel_cuda(at::TensorIteratorBase&)"

@@ -886,7 +886,7 @@ rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_
     fill_params(s, prob, nullptr, d, h_t);
     bind_workspace(s, *w, *t);
     RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
-    RD_CHECK(hipMemsetAsync(w->proto.st, 0, sizeof(State), st));   // done = 0: column pass active
+    RD_CHECK(hipMemsetAsync(w->proto.st, 0, sizeof(State), st));   // unfinished State: the passes run
     k.tin(w->slot_list_dev, 1, w_in, nullptr, st);
     if (d.dim == 3) {
         k.yfwd(w->slot_list_dev, 1, st, nullptr);

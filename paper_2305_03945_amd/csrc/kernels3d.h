@@ -260,7 +260,7 @@ template <typename T, int LOGN, int BC, int EQ, int KIND>
 __device__ __forceinline__ void row3_forward_pass(SlotRef s, StateRef sst, cplx<T> *buf, double *scratch) {
     constexpr int N = 1 << LOGN, H = N / 2;
     constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
-    constexpr int R = rows_per_block<T, LOGN, C>();
+    constexpr int R = rows_per_block3<T, LOGN, C>();
     constexpr int NREG = C * R / 2;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int z = tile / (N / R), y0 = (tile % (N / R)) * R;
@@ -298,7 +298,7 @@ __device__ __forceinline__ void row3_forward_pass(SlotRef s, StateRef sst, cplx<
 template <typename T, int LOGN, int BC, int EQ, int KIND>
 __global__ __launch_bounds__(NT) void k3_row_forward(Slot *const *slots) {
     constexpr int C = EQ == EQ_SCHNAK ? 2 : 1;
-    constexpr int NREG = C * rows_per_block<T, LOGN, C>() / 2;
+    constexpr int NREG = C * rows_per_block3<T, LOGN, C>() / 2;
     __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
     __shared__ double scratch[2 * C * (NT / 64)];
     SlotRef s = slot_of(slots);
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(NT) void k3_row_forward(Slot *const *slots) {
 template <typename T, int LOGN, int BC, int C>
 __global__ __launch_bounds__(NT) void k3_rowinv(Slot *const *slots) {
     constexpr int N = 1 << LOGN, H = N / 2;
-    constexpr int R = rows_per_block<T, LOGN, C>();
+    constexpr int R = rows_per_block3<T, LOGN, C>();
     constexpr int NREG = C * R / 2;
     constexpr size_t NN = (size_t)N * N * N;
     __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
@@ -770,7 +770,7 @@ __global__ __launch_bounds__((line_threads<T, LOGN>())) void k3_lines(Slot *cons
 template <typename T, int LOGN, int BC, int C>
 __global__ __launch_bounds__(NT) void k3_rows_transform_in(Slot *const *slots, const double *W) {
     constexpr int N = 1 << LOGN, H = N / 2;
-    constexpr int R = rows_per_block<T, LOGN, C>();
+    constexpr int R = rows_per_block3<T, LOGN, C>();
     constexpr int NREG = C * R / 2;
     constexpr size_t NN = (size_t)N * N * N;
     __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];
@@ -798,7 +798,7 @@ __global__ __launch_bounds__(NT) void k3_rows_transform_in(Slot *const *slots, c
 template <typename T, int LOGN, int BC, int C>
 __global__ __launch_bounds__(NT) void k3_rows_transform_out(Slot *const *slots, double *Y) {
     constexpr int N = 1 << LOGN, H = N / 2;
-    constexpr int R = rows_per_block<T, LOGN, C>();
+    constexpr int R = rows_per_block3<T, LOGN, C>();
     constexpr int NREG = C * R / 2;
     constexpr size_t NN = (size_t)N * N * N;
     __shared__ cplx<T> buf[NREG * lds_region<LOGN>()];

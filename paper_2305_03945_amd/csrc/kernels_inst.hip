@@ -21,6 +21,7 @@ inline hipEvent_t ev_start(hipEvent_t *ev) { return ev ? ev[0] : nullptr; }
 inline hipEvent_t ev_stop(hipEvent_t *ev) { return ev ? ev[1] : nullptr; }
 
 template <typename T, int EQ> constexpr int row_block() { return rows_per_block<T, L, ncomp<EQ>()>(); }
+template <typename T, int EQ> constexpr int row_block3() { return rows_per_block3<T, L, ncomp<EQ>()>(); }
 
 // The row kernel writes per-workgroup partial sums; the stop decision is taken
 // by k_finalize (launch_fin) or by the extra workgroup of the next column pass.
@@ -120,7 +121,7 @@ template <int BC, int EQ> void fill_mixed() {
 // ---------------------------------------------------------------- 3-D launchers
 template <typename T, int BC, int EQ, int KIND>
 void launch3_rowfwd_fin(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
-    constexpr int R = row_block<T, EQ>();
+    constexpr int R = row_block3<T, EQ>();
     constexpr int N = 1 << L;
     hipExtLaunchKernelGGL((k3_row_forward<T, L, BC, EQ, KIND>), dim3(N * (N / R), nslots), dim3(NT), 0, st,
                           ev_start(ev), nullptr, 0, slots);
@@ -141,7 +142,7 @@ void launch3_lines(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *e
 
 template <typename T, int BC, int EQ, int KIND>
 void launch3_rowfwd(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
-    constexpr int R = row_block<T, EQ>();
+    constexpr int R = row_block3<T, EQ>();
     constexpr int N = 1 << L;
     hipExtLaunchKernelGGL((k3_row_forward<T, L, BC, EQ, KIND>), dim3(N * (N / R), nslots), dim3(NT), 0, st,
                           ev_start(ev), ev_stop(ev), 0, slots);
@@ -149,7 +150,7 @@ void launch3_rowfwd(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *
 
 template <typename T, int BC, int EQ>
 void launch3_rowinv(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
-    constexpr int R = row_block<T, EQ>();
+    constexpr int R = row_block3<T, EQ>();
     constexpr int N = 1 << L;
     hipExtLaunchKernelGGL((k3_rowinv<T, L, BC, ncomp<EQ>()>), dim3(N * (N / R), nslots), dim3(NT), 0, st,
                           ev_start(ev), ev_stop(ev), 0, slots);
@@ -163,7 +164,7 @@ void launch3_upd(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev)
 
 template <typename T, int BC, int EQ>
 void launch3_tin(Slot *const *slots, int nslots, const double *in, double *, hipStream_t st) {
-    constexpr int R = row_block<T, EQ>();
+    constexpr int R = row_block3<T, EQ>();
     constexpr int N = 1 << L;
     hipLaunchKernelGGL((k3_rows_transform_in<T, L, BC, ncomp<EQ>()>), dim3(N * (N / R), nslots), dim3(NT), 0, st,
                        slots, in);
@@ -171,7 +172,7 @@ void launch3_tin(Slot *const *slots, int nslots, const double *in, double *, hip
 
 template <typename T, int BC, int EQ>
 void launch3_tout(Slot *const *slots, int nslots, const double *, double *out, hipStream_t st) {
-    constexpr int R = row_block<T, EQ>();
+    constexpr int R = row_block3<T, EQ>();
     constexpr int N = 1 << L;
     hipLaunchKernelGGL((k3_rows_transform_out<T, L, BC, ncomp<EQ>()>), dim3(N * (N / R), nslots), dim3(NT), 0, st,
                        slots, out);
@@ -192,7 +193,7 @@ template <typename T, int BC, int EQ, int MODE> void fill3_mode(KSet &k) {
     k.upd = launch3_upd<T, BC, EQ, MODE>;
     k.tin = launch3_tin<T, BC, EQ>;
     k.tout = launch3_tout<T, BC, EQ>;
-    k.rows_per_block = row_block<T, EQ>();
+    k.rows_per_block = row_block3<T, EQ>();
     k.dim = 3;
 }
 

@@ -150,8 +150,9 @@ __device__ __forceinline__ int dct_pos(int x, int N) { return (x & 1) ? (N - 1 -
 // spans at least four workgroups), and for two components at most half that.
 // Where one team spans the workgroup (N >= 16 NT), FP32 workgroups take two
 // row pairs, transformed in turn, so that the spectrum tiles are four rows high
-// and the column pass reads 128-byte runs.
-template <typename T, int LOGN, int C> constexpr int rows_per_block() {
+// and the column pass reads 128-byte runs.  This is the row count of the 3-D
+// row passes.
+template <typename T, int LOGN, int C> constexpr int rows_per_block3() {
     constexpr int N = 1 << LOGN;
     constexpr int teams = (N / 16 >= NT) ? 1 : NT / (N / 16);
     constexpr int pairs = (N / 16 >= NT && sizeof(T) == 4) ? 2 : 1;
@@ -159,6 +160,23 @@ template <typename T, int LOGN, int C> constexpr int rows_per_block() {
     constexpr int cap = N / 4;
     constexpr int r = want < 2 ? 2 : (want > cap ? cap : want);
     return r;
+}
+
+// 2-D row passes: below 2048^2 the rule above leaves few workgroups (N = 128:
+// 4 of 32 rows, N = 512: 32 of 16), and a pass waits on their serial stencil
+// loops while most CUs idle.  At most N/256 rows (at least 2: N/2 workgroups
+// up to N = 512, 256 at N = 1024) leave transform teams idle instead and are
+// faster on every grid measured (steps, ms: 128^2 FCH 7.9 -> 6.6, 256^2
+// Allen-Cahn 0.84 -> 0.63, 256^2 Neumann Cahn-Hilliard 1.04 -> 0.69, 512^2
+// 1.07 -> 0.82, 1024^2 1.39 -> 1.25; N/32, N/64 and N/128 rows measured in
+// between).  2048^2 and 4096^2 keep 4 rows.  The 3-D row passes keep theirs:
+// there the stop decision reduces one partial sum per workgroup of N^2 / R,
+// and more of them slowed the y pass that takes it.
+template <typename T, int LOGN, int C> constexpr int rows_per_block() {
+    constexpr int N = 1 << LOGN;
+    constexpr int r3 = rows_per_block3<T, LOGN, C>();
+    constexpr int small = N / 256 < 2 ? 2 : N / 256;
+    return r3 < small ? r3 : small;
 }
 
 }  // namespace rdk

@@ -206,6 +206,37 @@ def test_in_place_step_equals_out_of_place(ctx, rd, precision, dim):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_step_independent_of_schedule_history(rd, precision, dim):
+    """The host enqueues a step's iterations in chunks whose length it predicts from
+    the previous steps on the same workspace; the device decides every inner loop,
+    outer update and stop itself.  A step run after steps of very different length
+    (so its first chunk is far too long or far too short) gives bitwise the result,
+    iterations and outer passes of the same step in a fresh context."""
+    N = 64 if dim == 2 else 16
+    cfg = small_cfg("allen_cahn", N, "periodic")
+    cfg["dim"] = dim
+    p = rd.problem_from_config(cfg)
+    o = gpu_opts(rd, cfg, precision, tol=1e-8)
+    U0 = wl.uniform_field(N, -0.5, 0.5, 16, dim)
+    fresh = rd.Context(0)
+    try:
+        ref, iref = fresh.step(dev(U0), 1e-3, p, o)
+    finally:
+        fresh.close()
+    for history in ([1e-6, 1e-6, 1e-6], [1e-2, 3e-2, 5e-2]):   # short steps, then long ones
+        c = rd.Context(0)
+        try:
+            for ht in history:
+                c.step(dev(U0), ht, p, o)
+            u, info = c.step(dev(U0), 1e-3, p, o)
+            assert info["status"] == "ok" and info["iters"] == iref["iters"] and info["outer"] == iref["outer"]
+            assert np.array_equal(u.cpu().numpy(), ref.cpu().numpy()), history
+        finally:
+            c.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_unaligned_output_buffer(ctx, rd, precision):
     """The result reaches an output buffer at any 8-byte offset (the device-side copy
     needs 32-byte alignment; other buffers take the host-enqueued copy): bitwise the

@@ -48,6 +48,26 @@ void launch_copy_out(Slot *const *slots, double *out, size_t n, hipStream_t st) 
     hipLaunchKernelGGL(k_copy_out, dim3(blocks), dim3(NT), 0, st, slots, out, n);
 }
 
+// Serving: the finished steps of a batch of slots (blockIdx.y) replace their
+// trajectories' resident states, which are the steps' inputs (src); a slot whose
+// step still runs is left alone.  The input is read only by the initial pass, so
+// once the step has finished it may be overwritten.
+__global__ __launch_bounds__(NT) void k_copy_back(Slot *const *slots, size_t n) {
+    SlotRef s = slot_of(slots);
+    StateRef sst = state_of(s);
+    if (!sst.outer_done) return;
+    const double *src = s.mode == MODE_F64 ? (const double *)s.U[sst.iters & 1] : s.U64[sst.outer & 1];
+    const auto in4 = gp((const vec4_t<double> *)src);
+    const auto out4 = gp((vec4_t<double> *)const_cast<double *>(s.src));
+    for (size_t i = blockIdx.x * (size_t)NT + threadIdx.x; i < n / 4; i += (size_t)gridDim.x * NT) out4[i] = in4[i];
+}
+
+void launch_copy_back(Slot *const *slots, int nslots, size_t n, hipStream_t st) {
+    const size_t want = (n / 4 + NT - 1) / NT;
+    const int blocks = (int)(want < 2048 ? want : 2048);
+    hipLaunchKernelGGL(k_copy_back, dim3(blocks, nslots), dim3(NT), 0, st, slots, n);
+}
+
 void launch_prox(int eq, const Slot *slot_dev, int N, const double *c, double *u, hipStream_t st) {
     const int blocks = (int)(((size_t)N * N + NT - 1) / NT);
     if (eq == EQ_LAP5) hipLaunchKernelGGL((k_prox<EQ_LAP5>), dim3(blocks), dim3(NT), 0, st, slot_dev, c, u);

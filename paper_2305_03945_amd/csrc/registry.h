@@ -49,5 +49,7 @@ void launch_prox(int eq, const Slot *slot_dev, int N, const double *c, double *u
 // Copy of a finished step's result (n doubles, n % 4 == 0) to out; a no-op while
 // the slot's step runs.
 void launch_copy_out(Slot *const *slots, double *out, size_t n, hipStream_t st);
+// Serving: each finished slot's result (n doubles, n % 4 == 0) to its src buffer.
+void launch_copy_back(Slot *const *slots, int nslots, size_t n, hipStream_t st);
 
 }  // namespace rdk

@@ -1112,21 +1112,21 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
         iters = std::min(iters, 64);
         for (Traj *t : kv.second) t->issued += iters;
         enqueue_round(k, dev, (int)kv.second.size(), iters, st);
+        // steps that finish in this round: U^{k+1} becomes the resident state on the
+        // device, before the host has looked at any State
+        launch_copy_back(dev, (int)kv.second.size(), (size_t)kv.second.front()->d.C * kv.second.front()->d.pts, st);
         RD_CHECK(hipGetLastError());
         for (Traj *t : kv.second)
             RD_CHECK(hipMemcpyAsync(t->ws->st_host, t->ws->proto.st, sizeof(State), hipMemcpyDeviceToHost, st));
     }
     for (auto &kv : gstream) RD_CHECK(hipStreamSynchronize(kv.second));
-    // 4. retire finished steps: U^{k+1} becomes the resident state
+    // 4. retire finished steps (their results are already resident)
     for (auto &kv : running) {
-        hipStream_t st = gstream[kv.first];
         for (Traj *t : kv.second) {
             Workspace &w = *t->ws;
             const State &s = *w.st_host;
             const bool fin = w.mode == MODE_F64 ? s.done != 0 : s.outer_done != 0;
             if (!fin) continue;
-            RD_CHECK(hipMemcpyAsync(t->u, final_buffer(w, s), field_bytes(t->d.pts, t->d.C, 8),
-                                    hipMemcpyDeviceToDevice, st));
             Ticket &tk = c->tickets[t->running_ticket];
             info_from_state(s, w.mode, &tk.info);
             tk.done = true;
@@ -1134,7 +1134,6 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
             t->running = false;
         }
     }
-    for (auto &kv : gstream) RD_CHECK(hipStreamSynchronize(kv.second));
     return RD_OK;
 }
 

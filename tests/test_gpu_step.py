@@ -87,6 +87,19 @@ def test_step_periodic_large_columns(ctx, rd, kind, N):
 
 
 @pytest.mark.parametrize("kind", ["allen_cahn", "schnakenberg"])
+def test_step_neumann_512(ctx, rd, kind):
+    """Neumann (DCT-II) grid of 512^2, two rows per row workgroup: one step in FP64
+    (equal iterations, 1e-10) and in mixed precision (1e-5)."""
+    cfg = small_cfg(kind, 512, "neumann")
+    tol = 1e-7 if kind == "allen_cahn" else 1e-5
+    U0 = wl.initial_field(cfg, N=512, seed=17)
+    U1 = compare_fp64(ctx, rd, cfg, U0, 1, tol=tol)
+    Ug, info = ctx.step(dev(U0), cfg["ht"], rd.problem_from_config(cfg), gpu_opts(rd, cfg, "mixed", tol=tol))
+    assert info["status"] == "ok" and info["residual"] <= tol
+    assert max_abs(Ug.cpu().numpy(), U1) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["allen_cahn", "schnakenberg"])
 def test_step_fp64_prox_init_matches_oracle(ctx, rd, kind):
     cfg = small_cfg(kind, 64, "periodic")
     tol = 1e-8 if kind == "allen_cahn" else 1e-7

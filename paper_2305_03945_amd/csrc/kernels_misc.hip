@@ -31,12 +31,14 @@ void launch_residual(int bc, int eq, const Slot *slot_dev, int N, const double *
 // Result of a finished step -> the caller's buffer (n doubles, n % 4 == 0): the
 // FP64 iterate U[iters & 1] or the mixed path's FP64 U64[outer & 1].  Returns at
 // once while the step still runs, so the host enqueues it after every chunk of
-// iterations and needs no launch of its own once the step has finished.
+// iterations and needs no launch of its own once the step has finished; and when
+// that buffer is the caller's (the host may bind the output as one of the two).
 __global__ __launch_bounds__(NT) void k_copy_out(Slot *const *slots, double *out, size_t n) {
     SlotRef s = slot_of(slots);
     StateRef sst = state_of(s);
     if (!sst.outer_done) return;
     const double *src = s.mode == MODE_F64 ? (const double *)s.U[sst.iters & 1] : s.U64[sst.outer & 1];
+    if (src == out) return;   // the step ended in the caller's buffer
     const auto in4 = gp((const vec4_t<double> *)src);
     const auto out4 = gp((vec4_t<double> *)out);
     for (size_t i = blockIdx.x * (size_t)NT + threadIdx.x; i < n / 4; i += (size_t)gridDim.x * NT) out4[i] = in4[i];

@@ -137,6 +137,7 @@ struct Workspace {
     // iteration launches the last two steps on this workspace used (FP64: their
     // iterations; mixed: their inner iterations plus one per outer update)
     int last_iters = 0, prev_iters = 0;
+    int last_parity = -1;   // index of the iterate buffer the previous step ended in
 };
 
 // Record the length of a finished step for the next step's schedule.  A mixed
@@ -145,6 +146,7 @@ struct Workspace {
 void remember_step(Workspace &w, const State &s) {
     w.prev_iters = w.last_iters;
     w.last_iters = w.mode == MODE_F64 ? s.iters : s.total_iters + s.outer;
+    w.last_parity = w.mode == MODE_F64 ? (s.iters & 1) : (s.outer & 1);
 }
 
 // Iterations the first chunk of a step enqueues: what the previous step used,
@@ -630,9 +632,22 @@ rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double
     fill_params(s, prob, opts, d, h_t);
     bind_workspace(s, *w, *t);
     s.src = u_n;
-    RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
     const size_t n = (size_t)d.C * d.pts;
     const bool dev_copy = ((uintptr_t)u_np1 % 32) == 0 && n % 4 == 0;
+    // The output serves as the FP64 iterate buffer the previous step ended in (that
+    // index is as steady as the step's length), so a step that ends there needs no
+    // copy.  Buffer 0 is written by the initial pass while it reads u_n, so it is
+    // taken only when the output does not overlap u_n.
+    if (dev_copy && w->last_parity >= 0) {
+        const int p = w->last_parity;
+        const char *a = (const char *)u_np1, *b = (const char *)u_n;
+        const size_t bytes = n * sizeof(double);
+        if (p == 1 || !(a < b + bytes && b < a + bytes)) {
+            if (mode == MODE_F64) s.U[p] = u_np1;
+            else s.U64[p] = u_np1;
+        }
+    }
+    RD_CHECK(hipMemcpyAsync(w->slot_dev, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
     if ((r = run_step(c, *w, k, st, opts->max_iter, opts->max_outer, dev_copy ? u_np1 : nullptr, n)) != RD_OK)
         return r;
     const State &sf = *w->st_host;

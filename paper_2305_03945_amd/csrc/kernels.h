@@ -29,27 +29,25 @@
 
 namespace rdk {
 
-// ---------------------------------------------------------------- kinds of row-forward pass
-enum {
-    K_INIT64 = 0,     // FP64 path: U_0 from u_n, U^k copy, W_0 = F(U_0)
-    K_ITER64 = 1,     // FP64 path: W_{n+1} = F(U_{n+1})
-    K_INNER32 = 2,    // mixed: W = F~(e_{n+1}) in FP32
-    K_OUTER_INIT = 3, // mixed: U from u_n, r = F(U) in FP64, inner loop starts
-    K_OUTER_UPD = 4,  // mixed: U += e (FP64), r = F(U) in FP64, next inner loop
-    K_MIXED = 5       // mixed iteration pass: K_INNER32 while the inner loop runs,
-                      // K_OUTER_UPD once it has stopped (read from the State)
-};
-
 // ---------------------------------------------------------------- pointwise reaction prox
 // Implicit reaction-only step at one point (predictor for U_0): Allen-Cahn
 // u + h_t b (u^3 - u) = c by Newton from u = c (strictly increasing when
-// h_t b < 1); Schnakenberg by eliminating v and Newton on u.  Fixed iteration
-// counts keep the result independent of the data.
+// h_t b < 1); Schnakenberg by eliminating v and Newton on u.  Each Newton loop
+// stops once a step moves u by at most 2^-50 |u| (from there the quadratic
+// convergence has reached round-off; 3-6 steps for |c| <= 1) or after
+// PROX_MAX_NEWTON steps, a bound only far-out inputs approach.
+constexpr int PROX_MAX_NEWTON = 40;
+__device__ __forceinline__ bool newton_converged(double d, double u) { return !(fabs(d) > 0x1p-50 * fabs(u)); }
+
 __device__ __forceinline__ double prox_ac(double c, double ht, double b) {
     const double al = ht * b, be = 1.0 - ht * b;
     double u = c;
 #pragma unroll 1
-    for (int i = 0; i < 40; ++i) u -= (al * u * u * u + be * u - c) / (3.0 * al * u * u + be);
+    for (int i = 0; i < PROX_MAX_NEWTON; ++i) {
+        const double d = (al * u * u * u + be * u - c) / (3.0 * al * u * u + be);
+        u -= d;
+        if (newton_converged(d, u)) break;
+    }
     return u;
 }
 __device__ __forceinline__ void prox_schnak(double cu, double cv, double ht, double a, double b, double kap,
@@ -57,11 +55,13 @@ __device__ __forceinline__ void prox_schnak(double cu, double cv, double ht, dou
     const double gam = ht * kap, B = cv + gam * b;
     u = cu;
 #pragma unroll 1
-    for (int i = 0; i < 40; ++i) {
-        const double d = 1.0 + gam * u * u;
-        const double phi = u - cu - gam * (a - u + u * u * B / d);
-        const double dphi = 1.0 + gam - gam * B * 2.0 * u / (d * d);
-        u -= phi / dphi;
+    for (int i = 0; i < PROX_MAX_NEWTON; ++i) {
+        const double dd = 1.0 + gam * u * u;
+        const double phi = u - cu - gam * (a - u + u * u * B / dd);
+        const double dphi = 1.0 + gam - gam * B * 2.0 * u / (dd * dd);
+        const double d = phi / dphi;
+        u -= d;
+        if (newton_converged(d, u)) break;
     }
     v = B / (1.0 + gam * u * u);
 }
@@ -312,19 +312,10 @@ template <int K> __device__ __forceinline__ void block_sum(double *v, double *sc
     }
 }
 
-__device__ __forceinline__ bool finite_(double x) { return x == x && x - x == 0.0; }
-
-// Slot stop decision after a residual reduction (thread 0 of the last workgroup).
+// Slot stop decision after a residual reduction (thread 0 of the deciding
+// workgroup): the decision rule of rd_types.h on the State read coherently.
 template <int KIND, int C>
 __device__ __forceinline__ void finalize(SlotRef s, const double *sumsq, const double *mass) {
-    if constexpr (KIND == K_MIXED) {
-        // the row pass being decided made the outer update iff the inner loop had
-        // stopped when it started; the State has not changed since
-        if (state_of(s).done) finalize<K_OUTER_UPD, C>(s, sumsq, mass);
-        else finalize<K_INNER32, C>(s, sumsq, mass);
-        return;
-    }
-    State *st = s.st;
     double res = 0.0, m = 0.0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -332,84 +323,9 @@ __device__ __forceinline__ void finalize(SlotRef s, const double *sumsq, const d
         m += mass[c];
     }
     res /= s.ht;
-    const bool fin = finite_(res);
-    if constexpr (KIND == K_INIT64) {
-        st->iters = 0;
-        st->total_iters = 0;
-        st->outer = 0;
-        st->res = res;
-        st->res0 = res;
-        st->outer_res = res;
-        st->mass = m;
-        int done = 1, status = ST_OK;
-        if (!fin) status = ST_NONFINITE;
-        else if (res <= s.tol) status = ST_OK;
-        else if (s.max_iter <= 0) status = ST_NOCONV;
-        else done = 0;
-        st->status = status;
-        st->done = done;
-        st->outer_done = done;
-    } else if constexpr (KIND == K_ITER64) {
-        const int it = st->iters + 1;
-        st->iters = it;
-        st->total_iters = it;
-        st->res = res;
-        st->outer_res = res;
-        st->mass = m;
-        int done = 1, status = ST_OK;
-        if (!fin || res > GROWTH_LIMIT * st->res0) status = ST_NONFINITE;
-        else if (res <= s.tol) status = ST_OK;
-        else if (it >= s.max_iter) status = ST_NOCONV;
-        else done = 0;
-        st->status = status;
-        st->done = done;
-        st->outer_done = done;
-    } else if constexpr (KIND == K_INNER32) {
-        const int it = st->iters + 1;
-        st->iters = it;
-        st->total_iters = st->total_iters + 1;
-        st->inner_res = res;
-        if (!fin) {
-            st->status = ST_NONFINITE;
-            st->outer_done = 1;
-            st->done = 1;
-        } else {
-            int best_it = st->inner_best_it;
-            if (res < INNER_DROP * st->inner_best) {
-                st->inner_best = res;
-                best_it = it;
-                st->inner_best_it = it;
-            }
-            if (res <= st->inner_target || it >= s.max_iter || it - best_it >= INNER_STALL) st->done = 1;
-        }
-    } else {
-        int outer = 0;
-        if constexpr (KIND == K_OUTER_INIT) {
-            st->total_iters = 0;
-            st->res0 = res;
-        } else {
-            outer = st->outer + 1;
-        }
-        st->outer = outer;
-        st->outer_res = res;
-        st->res = res;
-        st->mass = m;
-        int odone = 1, status = ST_OK;
-        if (!fin || res > GROWTH_LIMIT * st->res0) status = ST_NONFINITE;
-        else if (res <= s.tol) status = ST_OK;
-        else if (outer >= s.max_outer || s.max_iter <= 0) status = ST_NOCONV;
-        else odone = 0;
-        st->status = status;
-        st->outer_done = odone;
-        st->done = odone;
-        st->iters = 0;
-        // the inner loop reduces the outer residual by inner_rtol, but need not go
-        // below half the step's tolerance: the next outer test then passes
-        st->inner_target = fmax(s.inner_rtol * res, 0.5 * s.tol);
-        st->inner_best = res;
-        st->inner_best_it = 0;
-    }
-    __threadfence();
+    State *st = s.st;
+    const StopRule rule{s.tol, s.inner_rtol, s.max_iter, s.max_outer};
+    store_state(st, decide<KIND>(load_state(st), rule, res, m));
 }
 
 // Write this workgroup's partial sums (squared residual norm and sum(U - U^k)

@@ -11,95 +11,92 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rd_types.h"
+
 namespace rdk {
-
-// Equation family: fixes the stencil shape and the number of components.
-//   EQ_LAP5   : +lambda Lap (5-point) with the Allen-Cahn reaction (b = 0: heat)
-//   EQ_BIH    : -lambda Lap Lap (13-point) with + Lap g(u) (b = 0: biharmonic)
-//   EQ_SCHNAK : two components, 5-point Laplacians, Schnakenberg kinetics
-//   EQ_FCH    : sixth-order functionalized Cahn-Hilliard (nested 5-point Laplacians,
-//               25-point reach), FP64 only
-enum { EQ_LAP5 = 0, EQ_BIH = 1, EQ_SCHNAK = 2, EQ_FCH = 3, EQ_COUNT = 4 };
-enum { BC_P = 0, BC_N = 1 };
-// Precision mode of a step: plain FP64 iteration, or FP32 inner iteration on a
-// correction with FP64 outer residual passes.
-enum { MODE_F64 = 0, MODE_MIXED = 1 };
-
-// Step status codes (same values as rd_status).
-enum { ST_OK = 0, ST_NOCONV = -2, ST_NONFINITE = -3 };
-
-constexpr int NT = 256;                 // threads per workgroup, every kernel
-constexpr double GROWTH_LIMIT = 1e8;    // residual growth that counts as divergence
 
 template <typename T> struct cplx { T re, im; };
 
-// Per-slot iteration state, written only by k_finalize (after the fixed-order
-// reduction of a residual pass) and read at the start of every kernel.
-struct State {
-    int done;          // inner loop finished (FP64 path: the whole step)
-    int iters;         // iterations of the current (inner) PDHG loop
-    int total_iters;   // mixed: inner iterations summed over outer passes
-    int outer;         // mixed: outer passes completed
-    int outer_done;    // mixed: step finished
-    int status;        // ST_*
-    int inner_best_it; // mixed: inner iteration of the last 10% drop of the inner norm
-    int pad;
-    double res;        // latest ||F/h_t|| of the current loop (FP64 path: paper norm)
-    double res0;       // paper norm at U_0
-    double outer_res;  // mixed: latest FP64 paper norm
-    double inner_target;
-    double mass;       // sum(U - U^k) at the latest FP64 residual evaluation
-    double inner_res;
-    double inner_best; // mixed: inner norm at inner_best_it
-};
-
-// The inner FP32 loop also ends when its norm has not dropped by INNER_DROP for
-// INNER_STALL iterations: it has reached the FP32 round-off floor of F~, and
-// further iterations cannot help the outer FP64 correction.
-constexpr int INNER_STALL = 32;
-constexpr double INNER_DROP = 0.9;
-
-struct Slot {
-    int N, ncomp, bc, eq;
-    int mode, max_iter, max_outer, init;
-    int nblk_rows, pad0, pad1, pad2;
-    double ht, h, inv_h2, inv_h4;
-    double diff[2];
-    double b;                    // Allen-Cahn / Cahn-Hilliard reaction coefficient
-    double sa, sb, kappa;        // Schnakenberg a, b, kappa
-    double tau_u, tau_p, omega, tol, inner_rtol;
-    double alpha[2], beta[2];    // G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2 per component
-    double gamma[2];
-    // Iterate buffers, element type T of the PDHG loop (double for FP64, float for
-    // the mixed inner loop), each [ncomp][N][N]:
-    void *U[2];                  // FP64: U_n ping-pong; mixed: correction e_n ping-pong
-    void *P, *Pt;                // dual variable and its extrapolation
-    void *S;                     // spectrum, [ncomp][N/2][N] complex, transposed
-    double *Uk;                  // U^k (FP64)
-    double *U64[2];              // mixed: FP64 U ping-pong across outer passes
-    float *r32, *Ub32;           // mixed: FP32 outer residual and FP32 copy of U
-    const double *src;           // caller's u_n
-    double *partials;            // [nblk_rows][2 * ncomp]
-    const double *eig;           // s_k, k < N, for this (N, bc, h)
-    const void *tw;              // exp(-2 pi i k / N), k < N, complex T
-    const void *twd;             // exp(-i pi k / (2N)), k < N, complex T
-    State *st;
-};
-
 // ---------------------------------------------------------------- address spaces
-// Slots and their States are read through the constant address space: the
-// fields are uniform across a workgroup, so they become scalar loads.  A kernel
-// never writes the slot it reads this way (State is written only by thread 0 of
-// k_finalize, through a plain pointer), and scalar caches are invalidated at
-// every kernel start, so the values seen are those of the previous launch.
+// Slots are read through the constant address space: the fields are uniform
+// across a workgroup, so they become scalar loads.  The host writes a slot
+// before the launches that read it and no kernel writes one.
 typedef const __attribute__((address_space(4))) Slot &SlotRef;
-typedef const __attribute__((address_space(4))) State &StateRef;
 __device__ __forceinline__ SlotRef slot_ref(const Slot *p) {
     return *(const __attribute__((address_space(4))) Slot *)p;
 }
 __device__ __forceinline__ SlotRef slot_of(Slot *const *slots) { return slot_ref(slots[blockIdx.y]); }
-__device__ __forceinline__ StateRef state_of(SlotRef s) {
-    return *(const __attribute__((address_space(4))) State *)s.st;
+
+// ---------------------------------------------------------------- the State, read coherently
+// The State is written by the stop decision of one launch and read by the
+// following launches (and, in a column pass or forward y pass, by the other
+// workgroups of the deciding launch itself).  Every read is a relaxed atomic
+// load at agent scope: a vector load that bypasses the non-coherent caches
+// (the per-CU vector L1 and the scalar cache), so its value never depends on
+// whether those caches were invalidated when the kernel was dispatched.  The
+// fields that select what a launch does are loaded once per thread and made
+// wave-uniform (readfirstlane).
+template <typename X> __device__ __forceinline__ X ld_agent(const X *p) {
+    return __hip_atomic_load((const __attribute__((address_space(1))) X *)p, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int uniform_(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+struct StateV {
+    int done, iters, outer, outer_done;
+};
+__device__ __forceinline__ StateV state_of(SlotRef s) {
+    const State *st = s.st;
+    StateV v;
+    v.done = uniform_(ld_agent(&st->done));
+    v.iters = uniform_(ld_agent(&st->iters));
+    v.outer = uniform_(ld_agent(&st->outer));
+    v.outer_done = uniform_(ld_agent(&st->outer_done));
+    return v;
+}
+typedef const StateV &StateRef;
+
+// The whole State, for the stop decision (one thread).
+__device__ __forceinline__ State load_state(const State *st) {
+    State v;
+    v.done = ld_agent(&st->done);
+    v.iters = ld_agent(&st->iters);
+    v.total_iters = ld_agent(&st->total_iters);
+    v.outer = ld_agent(&st->outer);
+    v.outer_done = ld_agent(&st->outer_done);
+    v.status = ld_agent(&st->status);
+    v.inner_best_it = ld_agent(&st->inner_best_it);
+    v.pad = 0;
+    v.res = ld_agent(&st->res);
+    v.res0 = ld_agent(&st->res0);
+    v.outer_res = ld_agent(&st->outer_res);
+    v.inner_target = ld_agent(&st->inner_target);
+    v.mass = ld_agent(&st->mass);
+    v.inner_res = ld_agent(&st->inner_res);
+    v.inner_best = ld_agent(&st->inner_best);
+    return v;
+}
+template <typename X> __device__ __forceinline__ void st_agent(X *p, X v) {
+    __hip_atomic_store((__attribute__((address_space(1))) X *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Stores the decided State; the release fence makes it visible device-wide
+// before the kernel ends.
+__device__ __forceinline__ void store_state(State *st, const State &v) {
+    st_agent(&st->done, v.done);
+    st_agent(&st->iters, v.iters);
+    st_agent(&st->total_iters, v.total_iters);
+    st_agent(&st->outer, v.outer);
+    st_agent(&st->outer_done, v.outer_done);
+    st_agent(&st->status, v.status);
+    st_agent(&st->inner_best_it, v.inner_best_it);
+    st_agent(&st->res, v.res);
+    st_agent(&st->res0, v.res0);
+    st_agent(&st->outer_res, v.outer_res);
+    st_agent(&st->inner_target, v.inner_target);
+    st_agent(&st->mass, v.mass);
+    st_agent(&st->inner_res, v.inner_res);
+    st_agent(&st->inner_best, v.inner_best);
+    __threadfence();
 }
 
 // Buffers are addressed through the global address space: pointers loaded from

@@ -4,7 +4,7 @@
 // size-independent kernels fill their own fields.
 #pragma once
 #include <hip/hip_runtime.h>
-#include "rd_dev.h"
+#include "rd_types.h"
 
 namespace rdk {
 

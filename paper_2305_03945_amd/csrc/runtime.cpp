@@ -182,6 +182,22 @@ size_t workspace_bytes(size_t pts, int rows, int C, int mode, int rows_per_block
     return b;
 }
 
+// Serving batch groups: steps that share a key run in one launch per kernel.
+struct GroupKey {
+    int mode, logN, bc, eq, dim;
+    bool operator<(const GroupKey &o) const {
+        return std::tie(mode, logN, bc, eq, dim) < std::tie(o.mode, o.logN, o.bc, o.eq, o.dim);
+    }
+};
+
+// Device slot-pointer list of one (group, role): role 0 for the init launch of
+// starting steps, role 1 for the iteration round.  A list is rewritten only in a
+// later pump round, after the stream that read it was synchronised.
+struct BatchBuffers {
+    Slot **dev = nullptr;
+    Slot **host = nullptr;
+    int cap = 0;
+};
 struct Ticket {
     rd_info info{};
     bool done = false;
@@ -207,6 +223,7 @@ struct Ctx {
     std::deque<Traj *> admit_queue;
     // one stream per concurrently advanced batch group (default priority)
     std::vector<hipStream_t> serve_streams;
+    std::map<std::pair<GroupKey, int>, BatchBuffers> batch;
 };
 
 // Batch groups advanced in one pump round run on separate streams, so that
@@ -591,6 +608,10 @@ rd_status rd_destroy(void *ctx) {
         }
     }
     for (hipStream_t q : c->serve_streams) (void)hipStreamDestroy(q);
+    for (auto &kv : c->batch) {
+        if (kv.second.dev) (void)hipFree(kv.second.dev);
+        if (kv.second.host) (void)hipHostFree(kv.second.host);
+    }
     if (c->scratch_slot_dev) (void)hipFree(c->scratch_slot_dev);
     if (c->scratch_slot_host) (void)hipHostFree(c->scratch_slot_host);
     if (c->scratch_partials) (void)hipFree(c->scratch_partials);
@@ -1005,26 +1026,10 @@ namespace {
 //     (N, bc, equation family, precision): one launch per kernel for all of them.
 //  4. Read back the states, retire finished steps: copy U^{k+1} to the resident
 //     state, record the ticket's info.
-struct GroupKey {
-    int mode, logN, bc, eq, dim;
-    bool operator<(const GroupKey &o) const {
-        return std::tie(mode, logN, bc, eq, dim) < std::tie(o.mode, o.logN, o.bc, o.eq, o.dim);
-    }
-};
-
-struct BatchBuffers {
-    Slot **dev = nullptr;
-    Slot **host = nullptr;
-    int cap = 0;
-};
-// Device slot-pointer lists per (context, group, role): role 0 for the init
-// launch of starting steps, role 1 for the iteration round.  A list is rewritten
-// only in a later pump round, after the stream that read it was synchronised.
-std::map<Ctx *, std::map<std::pair<GroupKey, int>, BatchBuffers>> g_batch;
 
 rd_status batch_list(Ctx *c, const GroupKey &key, int role, const std::vector<Traj *> &ts, Slot **&dev,
                      hipStream_t st) {
-    BatchBuffers &b = g_batch[c][std::make_pair(key, role)];
+    BatchBuffers &b = c->batch[std::make_pair(key, role)];
     const int n = (int)ts.size();
     if (b.cap < n) {
         if (b.dev) (void)hipFree(b.dev);

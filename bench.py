@@ -1,7 +1,7 @@
 #!/usr/bin/env python
 """Benchmark of the implicit reaction-diffusion step on one MI355X.
 
-Workload: 2-D Allen-Cahn u_t = eps^2 Lap u + u - u^3 on the periodic unit
+Headline workload: 2-D Allen-Cahn u_t = eps^2 Lap u + u - u^3 on the periodic unit
 square, 2048 x 2048 grid, eps = 0.01, backward Euler h_t = 1e-3, 200 steps,
 u0 ~ Uniform[-0.1, 0.1] (seed 1), stop at ||F/h_t||_2 <= 1e-6.  The same
 trajectory is run in plain FP64 and in the FP32-mixed precision (FP32 inner
@@ -10,8 +10,11 @@ PDHG solve of one implicit time step, inputs already resident in HBM.
 
 Prints ONE JSON line: throughput in grid-point-iterations/s (grid points x PDHG
 iterations per second; mixed: FP32 inner iterations), p50/p99 step latency for
-both precisions, the dominant kernel against the HBM roofline (HIP-event launch
-durations on the launch stream) and the CPU oracle timed on a bounded sample.
+both precisions, the PDHG iteration against the HBM roofline (algorithmic bytes
+per grid-point-iteration over the iteration's summed kernel durations, HIP events
+on the launch stream), the other configurations (64^2 Allen-Cahn, 512^2 Neumann
+Cahn-Hilliard, 1024^2 Schnakenberg) with their error against the oracle, the
+serving stream, and the CPU oracle timed on bounded samples.
 """
 import argparse
 import json
@@ -25,6 +28,14 @@ if ROOT not in sys.path:
 
 METRIC = "PDHG grid-point-iters/s + p50/p99 step latency, FP32-mixed vs FP64 at 1e-5"
 HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per grid-point-iteration of the whole PDHG iteration, one
+# component: the state read and written once (U, P read + write, U^k read; mixed:
+# e, P, r, U_b read, e, P written) plus one spectral round trip per transform
+# direction (the row pass writes the spectrum, the column pass reads and writes it,
+# the inverse row pass reads it).  A mixed outer FP64 pass moves 44 B per point.
+ALG_BYTES = {"fp64": 72, "mixed": 40}
+OUTER_BYTES = 44
 
 # Algorithmic HBM bytes per grid point and launch of each kernel (one component):
 # every field the kernel must read or write once, nothing for tables or halos.
@@ -88,7 +99,7 @@ def run_precision(ctx, rd, torch, cfg, u0, prec, steps, warmup):
     a.copy_(u0)
     torch.cuda.synchronize()
     lat, iters, outer, first = [], 0, 0, None
-    statuses = {}
+    statuses, mass = {}, []
     t0 = time.perf_counter()
     for k in range(steps):
         ts = time.perf_counter()
@@ -97,6 +108,7 @@ def run_precision(ctx, rd, torch, cfg, u0, prec, steps, warmup):
         iters += info["iters"]
         outer += info["outer"]
         statuses[info["status"]] = statuses.get(info["status"], 0) + 1
+        mass.append(abs(info["mass_drift"]))
         if k == 0:
             first = b.clone()
         a, b = b, a
@@ -106,25 +118,22 @@ def run_precision(ctx, rd, torch, cfg, u0, prec, steps, warmup):
     return dict(
         pt_iters_per_s=pts * iters / wall, wall_s=wall, ms_per_step=1e3 * wall / steps,
         p50_ms=1e3 * percentile(lat, 50), p99_ms=1e3 * percentile(lat, 99),
-        iters_total=iters, iters_per_step=iters / steps, outer_total=outer, status=statuses,
+        iters_total=iters, iters_per_step=iters / steps, outer_total=outer, outer_per_step=outer / steps,
+        status=statuses, max_abs_mass_drift_per_step=max(mass),
     ), first, a
 
 
-def cpu_oracle_sample(cfg, u0_np):
-    """The FP64 oracle (Algorithm 1, numpy) on the first step of the workload."""
-    from oracle import pdhg as opdhg
-    from tests.rd_cases import oracle_opts, oracle_problem
-    t0, c0 = time.perf_counter(), os.times()
-    r = opdhg.step(oracle_problem(cfg), u0_np, cfg["ht"], oracle_opts(cfg))
-    wall = time.perf_counter() - t0
-    c1 = os.times()
-    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+def cpu_oracle_sample(cfg, u0_np, wl):
+    """The FP64 oracle (Algorithm 1, numpy, one host core) on the first step of the
+    headline workload, plus the serving-stream sample."""
+    r, t = oracle_step(cfg, u0_np)
     N = cfg["N"]
-    return r, dict(value=N * N * r.iters / wall, unit="grid-point-iters/s", cores=max(1, round(cpu / wall)),
-                   kind="oracle", wall_s=round(wall, 3),
+    return r, dict(value=t["pt_iters_per_s"], unit="grid-point-iters/s", cores=t["cores"], kind="oracle",
+                   wall_s=round(t["step_ms"] / 1e3, 3),
                    sample="first implicit step of the %dx%d Allen-Cahn workload, %d PDHG iterations to the "
-                          "workload tolerance" % (N, N, r.iters),
-                   host=host_info(), other=oracle_other())
+                          "workload tolerance; numpy on one host core (the oracle is not parallelised)"
+                          % (N, N, r.iters),
+                   host=host_info(), serving=oracle_serving_sample(wl))
 
 
 def host_info():
@@ -139,20 +148,103 @@ def host_info():
     return dict(cpu_model=model, nproc=os.cpu_count(), omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
 
 
-def oracle_other():
-    """The oracle on the first steps of the two smaller 2-D workloads (64^2 Allen-Cahn,
-    512^2 Cahn-Hilliard): grid-point-iters/s and per-step latency, a few seconds in all."""
+def oracle_step(cfg, u0_np):
+    """The FP64 oracle (Algorithm 1, numpy, as it stands) on one step: result and timing."""
     from oracle import pdhg as opdhg
-    from paper_2305_03945_amd import workloads as wl
     from tests.rd_cases import oracle_opts, oracle_problem
-    out = {}
-    for name in ("ac64", "ch512"):
-        cfg = wl.CONFIGS[name]
-        u = wl.initial_field(cfg)
+    t0, c0 = time.perf_counter(), os.times()
+    r = opdhg.step(oracle_problem(cfg), u0_np, cfg["ht"], oracle_opts(cfg))
+    wall = time.perf_counter() - t0
+    c1 = os.times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    pts = cfg["N"] ** cfg.get("dim", 2)
+    return r, dict(pt_iters_per_s=pts * r.iters / wall, step_ms=1e3 * wall, iters=r.iters,
+                   cores=max(1, round(cpu / wall)))
+
+
+def oracle_serving_sample(wl, n_req=8, max_n=256):
+    """The oracle on serving requests alone, one after the other: the first n_req steps
+    of the stream (trajectory order) whose grid is at most max_n^2."""
+    from oracle import pdhg as opdhg
+    from tests.rd_cases import oracle_opts, oracle_problem
+    reqs = wl.serving_requests(64, 8, seed=5)
+    lat, pts_iters, done = [], 0, 0
+    t_all = time.perf_counter()
+    for r in reqs:
+        if r["cfg"]["N"] > max_n:
+            continue
+        cfg = r["cfg"]
         t0 = time.perf_counter()
-        r = opdhg.step(oracle_problem(cfg), u, cfg["ht"], oracle_opts(cfg))
-        wall = time.perf_counter() - t0
-        out[name] = dict(pt_iters_per_s=cfg["N"] ** 2 * r.iters / wall, step_ms=1e3 * wall, iters=r.iters)
+        res = opdhg.step(oracle_problem(cfg), r["u0"], cfg["ht"], oracle_opts(cfg))
+        lat.append(time.perf_counter() - t0)
+        pts_iters += cfg["N"] ** 2 * res.iters
+        done += 1
+        if done >= n_req:
+            break
+    wall = time.perf_counter() - t_all
+    return dict(requests=done, p50_ms=1e3 * percentile(lat, 50), max_ms=1e3 * max(lat),
+                pt_iters_per_s=pts_iters / wall,
+                sample="first %d steps of the serving stream with N <= %d, each alone" % (done, max_n))
+
+
+def iteration_roofline(kernels, results, N, steps):
+    """The PDHG iteration against the HBM roofline: ALG_BYTES per grid-point-iteration
+    x N^2 over the summed durations of the iteration's launches (HIP events on the
+    launch stream); the same over a whole step (mixed: inner iterations and outer FP64
+    passes); and the dominant kernel against its own bytes with its counted traffic."""
+    out = {}
+    for prec in ("mixed", "fp64"):
+        it_ms = sum(v["ms"] for v in kernels[prec].values())
+        b = ALG_BYTES[prec] * N * N
+        gbs = b / (it_ms * 1e-3) / 1e9
+        counted = [counted_traffic(prec, k, N.bit_length() - 1) for k in kernels[prec]]
+        r = results[prec]
+        step_bytes = (r["iters_per_step"] * ALG_BYTES[prec] + r["outer_per_step"] * OUTER_BYTES) * N * N
+        step_gbs = step_bytes / (r["ms_per_step"] * 1e-3) / 1e9
+        dom = max(kernels[prec], key=lambda k: kernels[prec][k]["ms"])
+        dk = kernels[prec][dom]
+        dt = counted_traffic(prec, dom, N.bit_length() - 1)
+        out[prec] = dict(
+            bytes_per_iteration=b, us_per_iteration=round(it_ms * 1e3, 2), achieved=round(gbs, 1),
+            frac=round(gbs / HBM_PEAK_GBS, 4),
+            traffic=None if any(c is None for c in counted) else round(sum(counted)),
+            launches=list(kernels[prec]),
+            step=dict(bytes_per_step=step_bytes, ms_per_step=r["ms_per_step"], achieved=round(step_gbs, 1),
+                      frac=round(step_gbs / HBM_PEAK_GBS, 4)),
+            dominant_kernel=dict(kernel=dom, bytes_per_launch=dk["bytes"], ms_per_launch=dk["ms"],
+                                 achieved=round(dk["gbs"], 1), frac=round(dk["gbs"] / HBM_PEAK_GBS, 4),
+                                 traffic=None if dt is None else round(dt)))
+    m = out["mixed"]
+    return dict(bound="hbm", kernel="PDHG iteration (%s), FP32-mixed inner loop" % ", ".join(m["launches"]),
+                achieved=m["achieved"], peak=HBM_PEAK_GBS, unit="GB/s", frac=m["frac"], traffic=m["traffic"],
+                traffic_unit="HBM bytes per iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                bytes_per_iteration=m["bytes_per_iteration"], us_per_iteration=m["us_per_iteration"],
+                bytes_per_grid_point_iteration=ALG_BYTES, mixed=m, fp64=out["fp64"])
+
+
+def config_leg(ctx, rd, torch, wl, name, precs, steps=None, oracle=True):
+    """One named configuration for its whole step count: per precision p50/p99 step
+    latency, grid-point-iterations/s, iterations (and outer passes) per step, the
+    largest per-step |mass drift|, and the max-abs difference of step 1 from the
+    oracle's step 1; the oracle's own timing of that step."""
+    import numpy as np
+    cfg = dict(wl.CONFIGS[name])
+    n = cfg["steps"] if steps is None else min(steps, cfg["steps"])
+    u0_np = wl.initial_field(cfg)
+    u0 = torch.tensor(u0_np, dtype=torch.float64, device="cuda")
+    out = dict(workload=name, N=cfg["N"], steps=n)
+    firsts = {}
+    for prec in precs:
+        out[prec], firsts[prec], _ = run_precision(ctx, rd, torch, cfg, u0, prec, n, 2)
+    if oracle:
+        ref, timing = oracle_step(cfg, u0_np)
+        out["oracle_step1"] = dict(timing, residual=ref.residual, status=ref.status)
+        for prec in precs:
+            out[prec]["step1_maxabs_vs_oracle"] = float(np.max(np.abs(firsts[prec].cpu().numpy() - ref.U)))
+    if "fp64" in precs and "mixed" in precs:
+        out["speedup_mixed_vs_fp64"] = out["fp64"]["wall_s"] / out["mixed"]["wall_s"]
+    del u0
+    torch.cuda.empty_cache()
     return out
 
 
@@ -230,23 +322,28 @@ def serving_leg(rd, torch, wl, n_traj, steps_per_traj):
                        % (n_traj, steps_per_traj))
 
 
+ADAPT = dict(ht0=0.4, eta=0.5, n_hi=50, n_lo=40, t_end=2.0)
+
+
 def adaptive_leg(ctx, rd, torch, cfg, u0):
     """The same trajectory with the adaptive step size of Sec. 2.2 (mixed precision):
-    h_t^0 = 50 h_t, eta = 0.75, N^* = 40, N_* = 15, over t in [0, 100 h_t]."""
+    h_t^0 = 0.4, eta = 0.5, N^* = 50, N_* = 40, over t in [0, 2].  From the noise the
+    first large step needs many iterations (shrink); as the field coarsens the counts
+    fall below N_* (enlarge)."""
     p = rd.problem_from_config(cfg)
     o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], omega=cfg["omega"], precision="mixed")
-    ht0 = 50 * cfg["ht"]
-    a = rd.make_adapt(ht0, 0.75, 40, 15)
-    t_end = 100 * cfg["ht"]
+    ht0 = ADAPT["ht0"]
+    a = rd.make_adapt(ht0, ADAPT["eta"], ADAPT["n_hi"], ADAPT["n_lo"])
+    t_end = ADAPT["t_end"]
     u = u0.clone()
-    ctx.advance(u, 2 * cfg["ht"], p, o, a)   # warm: workspaces and tables
+    ctx.advance(u, 2 * cfg["ht"], p, o, rd.make_adapt(cfg["ht"], 0.5, 1000, 1))   # warm: workspaces, tables
     u.copy_(u0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     info, trace = ctx.advance(u, t_end, p, o, a)
     wall = time.perf_counter() - t0
     N = cfg["N"]
-    return dict(t_end=t_end, ht0=ht0, eta=0.75, n_hi=40, n_lo=15, wall_s=wall,
+    return dict(t_end=t_end, ht0=ht0, eta=ADAPT["eta"], n_hi=ADAPT["n_hi"], n_lo=ADAPT["n_lo"], wall_s=wall,
                 pt_iters_per_s=N * N * info["pdhg_iters"] / wall, **info,
                 step_sizes=sorted(set(round(h, 12) for h, _, ok in trace if ok)))
 
@@ -405,23 +502,9 @@ def main():
             nbytes = BYTES_PER_POINT[prec][k] * N * N
             kernels[prec][k] = dict(ms=t, bytes=nbytes, gbs=nbytes / (t * 1e-3) / 1e9)
         log("  kernels %s: %s" % (prec, json.dumps(kernels[prec])))
-    head = "mixed"
-    dom = max(kernels[head], key=lambda k: kernels[head][k]["ms"])
-    dk = kernels[head][dom]
-    traffic = counted_traffic(head, dom, N.bit_length() - 1)
-    roofline = dict(bound="hbm", kernel=dom, achieved=round(dk["gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(dk["gbs"] / HBM_PEAK_GBS, 4), traffic=None if traffic is None else round(traffic),
-                    traffic_unit="bytes per launch", bytes_per_launch=dk["bytes"], ms_per_launch=dk["ms"])
-    # the whole iteration (all four kernels, back to back) against the same roofline
-    roofline["iteration"] = {}
-    for prec in ("fp64", "mixed"):
-        it_bytes = sum(v["bytes"] for v in kernels[prec].values())
-        it_ms = sum(v["ms"] for v in kernels[prec].values())
-        gbs = it_bytes / (it_ms * 1e-3) / 1e9
-        roofline["iteration"][prec] = dict(bytes=it_bytes, us=round(it_ms * 1e3, 2), achieved=round(gbs, 1),
-                                           frac=round(gbs / HBM_PEAK_GBS, 4))
-
-    log("adaptive step size: mixed, t in [0, %g]" % (100 * cfg["ht"]))
+    roofline = iteration_roofline(kernels, results, N, args.steps)
+    log("  roofline %s" % json.dumps(roofline))
+    log("adaptive step size: mixed, t in [0, %g]" % ADAPT["t_end"])
     adaptive = adaptive_leg(ctx, rd, torch, cfg, u0)
     log("  %s" % json.dumps(adaptive))
 
@@ -433,6 +516,13 @@ def main():
     examples = paper_examples_leg(ctx, rd, torch, wl, args.steps)
     log("  %s" % json.dumps({k: {p: v[p]["iters_per_step"] for p in v} for k, v in examples.items()
                              if k != "paper_counts"}))
+
+    configs = {}
+    for name, precs in (("ac64", ("fp64", "mixed")), ("ch512", ("fp64", "mixed")),
+                        ("schnak1024", ("mixed", "fp64"))):
+        log("configuration %s: %s" % (name, ", ".join(precs)))
+        configs[name] = config_leg(ctx, rd, torch, wl, name, precs, oracle=not args.no_cpu)
+        log("  %s" % json.dumps(configs[name]))
 
     log("3-D grid: 128^3 Allen-Cahn")
     grid3d = grid3d_leg(ctx, rd, torch, wl, args.steps)
@@ -448,7 +538,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("cpu oracle: first step at %dx%d" % (N, N))
-        ref, cpu = cpu_oracle_sample(cfg, u0_np)
+        ref, cpu = cpu_oracle_sample(cfg, u0_np, wl)
+        cpu["configs"] = {k: v.get("oracle_step1") for k, v in configs.items()}
         for prec in ("fp64", "mixed"):
             accuracy["%s_step1_maxabs_vs_oracle" % prec] = float(np.max(np.abs(firsts[prec].cpu().numpy() - ref.U)))
         accuracy["oracle_step1_iters"] = ref.iters
@@ -466,7 +557,8 @@ def main():
         "mixed": mx, "fp64": f64,
         "speedup_mixed_vs_fp64": f64["wall_s"] / mx["wall_s"],
         "accuracy": accuracy, "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu, "serving": serving,
-        "adaptive": adaptive, "grid3d": grid3d, "hbm4096": hbm4096, "paper_examples": examples,
+        "adaptive": adaptive, "configs": configs, "grid3d": grid3d, "hbm4096": hbm4096,
+        "paper_examples": examples,
     }
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -77,6 +77,43 @@ def test_ch512_first_step_fp64_and_mass(ctx, rd):
     assert abs(info["mass_drift"]) <= 512 * 1e-4 * info["residual"] + 1e-12
 
 
+def test_ch512_first_step_mixed_and_mass(ctx, rd):
+    """The 512^2 Neumann Cahn-Hilliard workload in the mixed precision, step 1: within 1e-5
+    of the oracle, and the FP64 mass drift of the final outer pass bounded by N h_t ||Res||."""
+    info = _first_step(ctx, rd, "ch512", "mixed", 1e-5)
+    assert info["outer"] >= 1
+    assert abs(info["mass_drift"]) <= 512 * 1e-4 * info["residual"] + 1e-12
+
+
+@pytest.fixture(scope="module")
+def ac2048_oracle_steps():
+    """The oracle's first three steps of the 2048^2 Allen-Cahn trajectory."""
+    cfg = wl.CONFIGS["ac2048"]
+    U = wl.initial_field(cfg)
+    out = []
+    for _ in range(3):
+        r = opdhg.step(oracle_problem(cfg), U, cfg["ht"], oracle_opts(cfg))
+        out.append(r)
+        U = r.U
+    return out
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_ac2048_three_steps_elementwise(ctx, rd, ac2048_oracle_steps, precision, bar):
+    """Steps 1-3 of the 2048^2 trajectory, every grid point against the oracle's, each GPU
+    step starting from the GPU's previous result (FP64: equal iteration counts)."""
+    cfg = wl.CONFIGS["ac2048"]
+    o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], omega=cfg["omega"], precision=precision)
+    p = rd.problem_from_config(cfg)
+    u = dev(wl.initial_field(cfg))
+    for k, ref in enumerate(ac2048_oracle_steps):
+        u, info = ctx.step(u, cfg["ht"], p, o)
+        assert info["status"] == "ok", (k, info)
+        if precision == "fp64":
+            assert info["iters"] == ref.iters, (k, info["iters"], ref.iters)
+        assert max_abs(u.cpu().numpy(), ref.U) <= bar, k
+
+
 def test_ac2048_sampled_residual_after_steps(ctx, rd):
     """Property at full size: after 5 steps, the oracle's F evaluated pointwise at sampled grid
     points from the GPU's U^{k+1}, U^k is consistent with the reported ||F/h_t||_2 <= tol."""

@@ -33,25 +33,34 @@ __device__ __forceinline__ SlotRef slot_of(Slot *const *slots) { return slot_ref
 // workgroups of the deciding launch itself).  Every read is a relaxed atomic
 // load at agent scope: a vector load that bypasses the non-coherent caches
 // (the per-CU vector L1 and the scalar cache), so its value never depends on
-// whether those caches were invalidated when the kernel was dispatched.  The
-// fields that select what a launch does are loaded once per thread and made
-// wave-uniform (readfirstlane).
+// whether those caches were invalidated when the kernel was dispatched.
 template <typename X> __device__ __forceinline__ X ld_agent(const X *p) {
     return __hip_atomic_load((const __attribute__((address_space(1))) X *)p, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ int uniform_(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 struct StateV {
     int done, iters, outer, outer_done;
 };
+// The four fields that select what a launch does, read once per workgroup (two
+// 8-byte loads by thread 0; one request per workgroup rather than per wave keeps
+// the thousands of workgroups of a launch from queueing on the one line) and
+// handed to every thread through LDS.  Called by every thread of the workgroup,
+// before any thread leaves the kernel.
 __device__ __forceinline__ StateV state_of(SlotRef s) {
-    const State *st = s.st;
+    __shared__ unsigned long long sh_state[2];
+    if (threadIdx.x == 0) {
+        const unsigned long long *p = (const unsigned long long *)s.st;
+        sh_state[0] = ld_agent(p);
+        sh_state[1] = ld_agent(p + 1);
+    }
+    __syncthreads();
+    const unsigned long long a = sh_state[0], b = sh_state[1];
     StateV v;
-    v.done = uniform_(ld_agent(&st->done));
-    v.iters = uniform_(ld_agent(&st->iters));
-    v.outer = uniform_(ld_agent(&st->outer));
-    v.outer_done = uniform_(ld_agent(&st->outer_done));
+    v.done = __builtin_amdgcn_readfirstlane((int)(unsigned)(a & 0xffffffffu));
+    v.iters = __builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+    v.outer = __builtin_amdgcn_readfirstlane((int)(unsigned)(b & 0xffffffffu));
+    v.outer_done = __builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
     return v;
 }
 typedef const StateV &StateRef;

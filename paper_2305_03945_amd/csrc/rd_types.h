@@ -37,11 +37,12 @@ constexpr double GROWTH_LIMIT = 1e8;    // residual growth that counts as diverg
 // fixed-order reduction of a residual pass), and read at the start of every
 // kernel with device-coherent loads (rd_dev.h).
 struct State {
+    // the four fields every launch branches on come first, in two 8-byte words
     int done;          // inner loop finished (FP64 path: the whole step)
     int iters;         // iterations of the current (inner) PDHG loop
-    int total_iters;   // mixed: inner iterations summed over outer passes
     int outer;         // mixed: outer passes completed
     int outer_done;    // mixed: step finished
+    int total_iters;   // mixed: inner iterations summed over outer passes
     int status;        // ST_*
     int inner_best_it; // mixed: inner iteration of the last 10% drop of the inner norm
     int pad;

@@ -141,6 +141,23 @@ size_t rd_footprint_bytes(const rd_problem *prob, const rd_opts *opts);
 rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
                   const double *u_n, double *u_np1, void *hip_stream, rd_info *info);
 
+/* ---- one implicit step without allocation ------------------------------------------ */
+/* For callers that cannot allocate device or pinned memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): rd_step with
+ * the same arguments, results and statuses (FP64 results bitwise equal to rd_step's; the
+ * mixed path's within its rounding), whose workspace, tables, slot and State live in a
+ * device scratch array of 64 MiB that the library holds on every device it runs on until
+ * the process ends.  The call allocates nothing: no hipMalloc / hipFree / pinned host
+ * memory; host staging is static.  Limits: N <= 1024 and a workspace that fits the 64 MiB
+ * (one component up to 1024^2 in either precision, two components up to 512^2; 3-D grids
+ * up to 64^3); larger problems return RD_E_NOMEM before any device work.  The scratch
+ * array is shared by every call on a device and keeps the last call's contents (each call
+ * rewrites what it reads first), so calls that overlap on one device -- from several
+ * threads or contexts, or on several streams -- race and must not be made.
+ * Synchronises the stream.                                                               */
+rd_status rd_step_noalloc(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
+                          const double *u_n, double *u_np1, void *hip_stream, rd_info *info);
+
 /* ---- adaptive time step size (Sec. 2.2, "Adaptive time stepsize") ---------------------- */
 /* Rule: after a step of size h that took M PDHG iterations (rd_info.iters; mixed: inner
  * iterations), the next step uses eta h if M > n_hi (N^*), h / eta if M < n_lo (N_*) and

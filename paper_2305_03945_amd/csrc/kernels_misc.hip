@@ -8,6 +8,17 @@ namespace rdk {
 KSet g_kernels[2][LOGN_MAX + 1][2][EQ_COUNT];
 KSet g_kernels3[2][LOGN3_MAX + 1][2][EQ_COUNT];
 
+// Workspace of rd_step_noalloc: every buffer its kernels use (slot, State, partial
+// sums, tables, iterate fields) is carved from this array, so that the entry point
+// allocates nothing.  Each device the library runs on holds its own copy for the
+// life of the process.  In host code the name is not a device address: host code
+// uses only the address noalloc_scratch_address() returns for the current device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+hipError_t noalloc_scratch_address(void **out) {
+    return hipGetSymbolAddress(out, HIP_SYMBOL(scratch));
+}
+
 void launch_residual(int bc, int eq, const Slot *slot_dev, int N, const double *U, const double *Uk, double *W,
                      double *partials, hipStream_t st) {
     const int blocks = (int)(((size_t)N * N + NT - 1) / NT);

@@ -42,6 +42,12 @@ RD_DECLARE_LOGN(4) RD_DECLARE_LOGN(5) RD_DECLARE_LOGN(6) RD_DECLARE_LOGN(7) RD_D
 RD_DECLARE_LOGN(9) RD_DECLARE_LOGN(10) RD_DECLARE_LOGN(11) RD_DECLARE_LOGN(12)
 #undef RD_DECLARE_LOGN
 
+// Bytes of the device scratch array behind rd_step_noalloc, and its device address
+// on the current device (hipGetSymbolAddress; call once per device, that device
+// current).
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+hipError_t noalloc_scratch_address(void **out);
+
 // Size-independent single-slot kernels used by the kernel-level entry points.
 void launch_residual(int bc, int eq, const Slot *slot_dev, int N, const double *U, const double *Uk, double *W,
                      double *partials, hipStream_t st);

@@ -323,11 +323,8 @@ rd_status make_workspace(const Desc &d, int mode, std::unique_ptr<Workspace> &ou
     return RD_OK;
 }
 
-void fill_tables_host(int N, int bc, double h, std::vector<double> &eig, std::vector<double> &tw,
-                      std::vector<double> &twd) {
-    eig.resize(N);
-    tw.resize(2 * N);
-    twd.resize(2 * N);
+// eig: N doubles; tw, twd: 2N doubles (complex, re/im interleaved).
+void fill_tables_host(int N, int bc, double h, double *eig, double *tw, double *twd) {
     const long double pi = 3.141592653589793238462643383279502884L;
     for (int k = 0; k < N; ++k) {
         const long double arg = (bc == BC_P) ? pi * k / N : pi * k / (2.0L * N);
@@ -351,8 +348,8 @@ rd_status get_tables(Ctx *c, int N, int bc, double h, Tables *&out) {
         out = &it->second;
         return RD_OK;
     }
-    std::vector<double> eig, tw, twd;
-    fill_tables_host(N, bc, h, eig, tw, twd);
+    std::vector<double> eig(N), tw(2 * N), twd(2 * N);
+    fill_tables_host(N, bc, h, eig.data(), tw.data(), twd.data());
     std::vector<float> tw32(tw.begin(), tw.end()), twd32(twd.begin(), twd.end());
     Tables t;
     RD_CHECK(hipMalloc((void **)&t.eig, N * sizeof(double)));
@@ -538,6 +535,43 @@ rd_status run_step(Ctx *c, Workspace &w, const KSet &k, hipStream_t st, int max_
     return RD_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free steps
+// rd_step_noalloc runs the kernels of rd_step on a workspace carved from the
+// device scratch array of kernels_misc.hip.  Per device: the array's address
+// (taken once, by rd_create, with the device current) and host-side staging that
+// lives in static storage, so that a call allocates nothing.  Calls that overlap
+// on one device share all of it and race.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+constexpr int NOALLOC_MAX_N = 1024;
+struct NoAllocDevice {
+    char *base = nullptr;        // device address of the scratch array
+    Slot slot{};                 // host staging of the slot
+    Slot *list = nullptr;        // host staging of the one-entry slot list
+    State st{};                  // host staging of the State (zeroed) and its readback
+    double eig[NOALLOC_MAX_N], tw[2 * NOALLOC_MAX_N], twd[2 * NOALLOC_MAX_N];
+    float tw32[2 * NOALLOC_MAX_N], twd32[2 * NOALLOC_MAX_N];
+    int last_iters = 0, prev_iters = 0;   // schedule history, as a Workspace keeps it
+};
+NoAllocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+std::mutex g_noalloc_mu;
+
+rd_status noalloc_setup(int device) {
+    if (device >= NOALLOC_MAX_DEVICES) return RD_OK;   // such devices serve rd_step only
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc[device].base) return RD_OK;
+    void *p = nullptr;
+    const hipError_t e = noalloc_scratch_address(&p);
+    if (e != hipSuccess || !p) {
+        if (std::getenv("RD_LOG"))
+            std::fprintf(stderr, "[rd] scratch address on device %d: %s\n", device, hipGetErrorString(e));
+        return RD_E_DEVICE;
+    }
+    g_noalloc[device].base = (char *)p;
+    return RD_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -578,10 +612,13 @@ rd_status rd_create(int device, void **out) {
     if (device < 0 || device >= n) return RD_E_INVALID;
     RD_CHECK(hipSetDevice(device));
     std::call_once(g_register_once, register_all);
+    rd_status r = noalloc_setup(device);
+    if (r != RD_OK) return r;
     auto *c = new Ctx();
     c->device = device;
     if (hipMalloc((void **)&c->scratch_slot_dev, sizeof(Slot)) != hipSuccess ||
         hipHostMalloc((void **)&c->scratch_slot_host, sizeof(Slot), hipHostMallocDefault) != hipSuccess) {
+        if (c->scratch_slot_dev) (void)hipFree(c->scratch_slot_dev);
         delete c;
         return RD_E_NOMEM;
     }
@@ -675,6 +712,121 @@ rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double
     if (!dev_copy) {
         RD_CHECK(hipMemcpyAsync(u_np1, final_buffer(*w, sf), field_bytes(d.pts, d.C, 8), hipMemcpyDeviceToDevice,
                                 st));
+        RD_CHECK(hipStreamSynchronize(st));
+    }
+    info_from_state(sf, mode, info);
+    return (rd_status)sf.status;
+}
+
+rd_status rd_step_noalloc(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t, const double *u_n,
+                          double *u_np1, void *hip_stream, rd_info *info) {
+    if (!ctx || !u_n || !u_np1) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    Desc d;
+    rd_status r = describe(prob, d);
+    if (r != RD_OK) return r;
+    if ((r = check_opts(opts)) != RD_OK) return r;
+    if (!(h_t > 0.0) || !std::isfinite(h_t)) return RD_E_INVALID;
+    const int mode = opts->precision == RD_FP32_MIXED ? MODE_MIXED : MODE_F64;
+    const KSet &k = kset(mode, d);
+    if (!k.init) return RD_E_INVALID;   // no such precision for the equation
+    if (c->device >= NOALLOC_MAX_DEVICES || !g_noalloc[c->device].base) return RD_E_DEVICE;
+    if (d.N > NOALLOC_MAX_N) return RD_E_NOMEM;
+    NoAllocDevice &na = g_noalloc[c->device];
+    RD_CHECK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    // the workspace of rd_step, carved from the scratch array (256-byte aligned pieces)
+    const int C = d.C;
+    const size_t te = mode == MODE_F64 ? 8 : 4;
+    const int nblk = d.rows / k.rows_per_block;
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t o_slot = take(sizeof(Slot)), o_list = take(sizeof(Slot *)), o_st = take(sizeof(State));
+    const size_t o_part = take((size_t)nblk * 2 * C * sizeof(double));
+    const size_t o_eig = take((size_t)d.N * sizeof(double));
+    const size_t o_tw = take(2 * (size_t)d.N * te), o_twd = take(2 * (size_t)d.N * te);
+    const size_t fb = field_bytes(d.pts, C, te), f64 = field_bytes(d.pts, C, 8), f32 = field_bytes(d.pts, C, 4);
+    const size_t o_u0 = take(fb), o_u1 = take(fb), o_p = take(fb), o_pt = take(fb), o_s = take(fb);
+    const size_t o_uk = take(f64);
+    size_t o_v0 = 0, o_v1 = 0, o_r = 0, o_ub = 0;
+    if (mode == MODE_MIXED) {
+        o_v0 = take(f64);
+        o_v1 = take(f64);
+        o_r = take(f32);
+        o_ub = take(f32);
+    }
+    if (off > NOALLOC_BYTES) return RD_E_NOMEM;
+    char *B = na.base;
+    // tables, in the iteration's precision
+    fill_tables_host(d.N, d.bc, d.h, na.eig, na.tw, na.twd);
+    RD_CHECK(hipMemcpyAsync(B + o_eig, na.eig, (size_t)d.N * sizeof(double), hipMemcpyHostToDevice, st));
+    if (mode == MODE_F64) {
+        RD_CHECK(hipMemcpyAsync(B + o_tw, na.tw, 2 * (size_t)d.N * sizeof(double), hipMemcpyHostToDevice, st));
+        RD_CHECK(hipMemcpyAsync(B + o_twd, na.twd, 2 * (size_t)d.N * sizeof(double), hipMemcpyHostToDevice, st));
+    } else {
+        for (int i = 0; i < 2 * d.N; ++i) {
+            na.tw32[i] = (float)na.tw[i];
+            na.twd32[i] = (float)na.twd[i];
+        }
+        RD_CHECK(hipMemcpyAsync(B + o_tw, na.tw32, 2 * (size_t)d.N * sizeof(float), hipMemcpyHostToDevice, st));
+        RD_CHECK(hipMemcpyAsync(B + o_twd, na.twd32, 2 * (size_t)d.N * sizeof(float), hipMemcpyHostToDevice, st));
+    }
+    // the slot, its one-entry list and a zeroed State
+    Slot &s = na.slot;
+    std::memset(&s, 0, sizeof(Slot));
+    fill_params(s, prob, opts, d, h_t);
+    s.U[0] = B + o_u0;
+    s.U[1] = B + o_u1;
+    s.P = B + o_p;
+    s.Pt = B + o_pt;
+    s.S = B + o_s;
+    s.Uk = (double *)(B + o_uk);
+    if (mode == MODE_MIXED) {
+        s.U64[0] = (double *)(B + o_v0);
+        s.U64[1] = (double *)(B + o_v1);
+        s.r32 = (float *)(B + o_r);
+        s.Ub32 = (float *)(B + o_ub);
+    }
+    s.partials = (double *)(B + o_part);
+    s.st = (State *)(B + o_st);
+    s.nblk_rows = nblk;
+    s.eig = (const double *)(B + o_eig);
+    s.tw = B + o_tw;
+    s.twd = B + o_twd;
+    s.src = u_n;
+    na.list = (Slot *)(B + o_slot);
+    std::memset(&na.st, 0, sizeof(State));
+    RD_CHECK(hipMemcpyAsync(B + o_slot, &s, sizeof(Slot), hipMemcpyHostToDevice, st));
+    RD_CHECK(hipMemcpyAsync(B + o_list, &na.list, sizeof(Slot *), hipMemcpyHostToDevice, st));
+    RD_CHECK(hipMemcpyAsync(B + o_st, &na.st, sizeof(State), hipMemcpyHostToDevice, st));
+    // the launch schedule of rd_step on a workspace that owns nothing
+    Workspace w;
+    w.N = d.N;
+    w.C = C;
+    w.mode = mode;
+    w.logN = d.logN;
+    w.nblk = nblk;
+    w.dim = d.dim;
+    w.pts = d.pts;
+    w.proto = s;
+    w.slot_dev = (Slot *)(B + o_slot);
+    w.slot_list_dev = (Slot **)(B + o_list);
+    w.st_host = &na.st;
+    w.last_iters = na.last_iters;
+    w.prev_iters = na.prev_iters;
+    const size_t n = (size_t)C * d.pts;
+    const bool dev_copy = ((uintptr_t)u_np1 % 32) == 0 && n % 4 == 0;
+    r = run_step(c, w, k, st, opts->max_iter, opts->max_outer, dev_copy ? u_np1 : nullptr, n);
+    na.last_iters = w.last_iters;
+    na.prev_iters = w.prev_iters;
+    if (r != RD_OK) return r;
+    const State &sf = na.st;
+    if (!dev_copy) {
+        RD_CHECK(hipMemcpyAsync(u_np1, final_buffer(w, sf), field_bytes(d.pts, C, 8), hipMemcpyDeviceToDevice, st));
         RD_CHECK(hipStreamSynchronize(st));
     }
     info_from_state(sf, mode, info);

@@ -28,7 +28,8 @@ STATUS_NAMES = {RD_OK: "ok", RD_E_INVALID: "invalid", RD_E_NOCONV: "noconv", RD_
                 RD_E_NOMEM: "nomem", RD_E_DEVICE: "device", RD_E_BUSY: "busy"}
 
 # Every C-ABI symbol include/rd.h declares.
-EXPORTED = ("rd_create", "rd_destroy", "rd_default_opts", "rd_footprint_bytes", "rd_step", "rd_residual",
+EXPORTED = ("rd_create", "rd_destroy", "rd_default_opts", "rd_footprint_bytes", "rd_step", "rd_step_noalloc",
+            "rd_residual",
             "rd_precond_solve", "rd_prox", "rd_profile_iteration", "rd_serve_set_budget", "rd_traj_open", "rd_traj_submit",
             "rd_serve_pump", "rd_poll", "rd_traj_read", "rd_traj_close", "rd_serve_stats", "rd_adapt_next",
             "rd_advance", "rd_status_str")
@@ -102,6 +103,7 @@ _sig = {
     "rd_default_opts": (None, [_P(Opts)]),
     "rd_footprint_bytes": (ctypes.c_size_t, [_P(Problem), _P(Opts)]),
     "rd_step": (ctypes.c_int, [_vp, _P(Problem), _P(Opts), ctypes.c_double, _vp, _vp, _vp, _P(Info)]),
+    "rd_step_noalloc": (ctypes.c_int, [_vp, _P(Problem), _P(Opts), ctypes.c_double, _vp, _vp, _vp, _P(Info)]),
     "rd_residual": (ctypes.c_int, [_vp, _P(Problem), ctypes.c_double, _vp, _vp, _vp, _vp, _P(ctypes.c_double)]),
     "rd_precond_solve": (ctypes.c_int, [_vp, _P(Problem), ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
     "rd_prox": (ctypes.c_int, [_vp, _P(Problem), ctypes.c_double, _vp, _vp, _vp]),
@@ -248,6 +250,17 @@ class Context:
         if code in raise_on:
             raise RDError(code, "rd_step")
         return out, info.as_dict()
+
+    def step_noalloc(self, u, ht, problem, opts, out, stream=None, raise_on=(RD_E_INVALID, RD_E_DEVICE)):
+        """rd_step_noalloc: one step whose workspace is the library's device scratch array
+        (the caller passes the output buffer; the call allocates nothing).  Returns
+        (info dict, status code); RD_E_NOMEM for problems beyond the scratch array."""
+        info = Info()
+        code = _lib.rd_step_noalloc(self._h, ctypes.byref(problem), ctypes.byref(opts), float(ht), _dptr(u, problem),
+                                    _dptr(out, problem), _stream_ptr(stream), ctypes.byref(info))
+        if code in raise_on:
+            raise RDError(code, "rd_step_noalloc")
+        return info.as_dict(), code
 
     # ---------------------------------------------------------- kernel-level calls
     def residual(self, u, uk, ht, problem, stream=None):

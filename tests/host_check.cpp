@@ -202,6 +202,11 @@ void fill(int L) {
 }  // namespace
 
 namespace rdk {
+static unsigned char g_scratch_host[NOALLOC_BYTES];
+hipError_t noalloc_scratch_address(void **out) {
+    *out = g_scratch_host;
+    return hipSuccess;
+}
 void register_upd_kernels() {}
 #define RD_REG(L) \
     void register_logn_##L() { fill(L); }
@@ -563,6 +568,46 @@ void column_pass_race_invariant() {
     }
 }
 
+// rd_step_noalloc: the results and counts of rd_step, on the scratch array, with no
+// allocation (the stub's live-allocation count does not move during the calls);
+// problems beyond the array are refused.
+void noalloc_steps() {
+    void *ctx = nullptr;
+    rd_create(0, &ctx);
+    for (int prec : {RD_FP64, RD_FP32_MIXED}) {
+        for (int N : {256, 32}) {
+            const size_t n = (size_t)N * N;
+            rd_problem p = ac(N);
+            rd_opts o = opts(prec == RD_FP64 ? 1e-3 : 1e-6, prec);
+            double *u = dalloc(n), *a = dalloc(n), *b = dalloc(n + 1);
+            for (size_t i = 0; i < n; ++i) u[i] = 0.125;
+            rd_info ia, ib;
+            CHECK(rd_step(ctx, &p, &o, 0.01, u, a, nullptr, &ia) == RD_OK);
+            const long live = hipstub::live_allocs();
+            CHECK(rd_step_noalloc(ctx, &p, &o, 0.01, u, b, nullptr, &ib) == RD_OK);
+            CHECK(rd_step_noalloc(ctx, &p, &o, 0.01, u, b + 1, nullptr, &ib) == RD_OK);   // unaligned output
+            CHECK(rd_step_noalloc(ctx, &p, &o, 0.01, u, u, nullptr, &ib) == RD_OK);       // in place
+            CHECK(hipstub::live_allocs() == live);
+            CHECK(ia.iters == ib.iters && ia.outer == ib.outer && ia.status == ib.status);
+            CHECK(std::memcmp(a, b + 1, n * sizeof(double)) == 0 && std::memcmp(a, u, n * sizeof(double)) == 0);
+            hipFree(u);
+            hipFree(a);
+            hipFree(b);
+        }
+    }
+    rd_problem big = ac(2048);
+    rd_opts o = opts(1e-3, RD_FP64);
+    double *u = dalloc(16);
+    rd_info info;
+    CHECK(rd_step_noalloc(ctx, &big, &o, 0.01, u, u, nullptr, &info) == RD_E_NOMEM);
+    big = ac(1024);
+    big.rx = RD_RX_SCHNAKENBERG;
+    big.diff[1] = 10.0;
+    CHECK(rd_step_noalloc(ctx, &big, &o, 0.01, u, u, nullptr, &info) == RD_E_NOMEM);
+    hipFree(u);
+    rd_destroy(ctx);
+}
+
 void teardown_returns_everything() {
     const long base = hipstub::live_allocs();
     for (int r = 0; r < 20; ++r) {
@@ -595,6 +640,7 @@ int main() {
     serving();
     adaptive();
     column_pass_race_invariant();
+    noalloc_steps();
     teardown_returns_everything();
     if (g_fail) {
         std::fprintf(stderr, "%d checks failed\n", g_fail);

@@ -2,6 +2,7 @@
 // the build) and registers the launchers.
 #include "kernels.h"
 #include "kernels3d.h"
+#include "kernels_wg.h"
 #include "registry.h"
 
 #include <hip/hip_ext.h>
@@ -84,6 +85,13 @@ void launch_tout(Slot *const *slots, int nslots, const double *, double *out, hi
                        slots, out);
 }
 
+// Small grids: the whole step in one launch, one workgroup per slot.
+template <typename T, int BC, int EQ, int MODE>
+void launch_step_wg(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *ev) {
+    hipExtLaunchKernelGGL((k_step_wg<T, L, BC, EQ, MODE>), dim3(1, nslots), dim3(NT7), 0, st, ev_start(ev),
+                          ev_stop(ev), 0, slots);
+}
+
 template <int BC, int EQ> void fill_mixed();
 
 template <int BC, int EQ> void fill() {
@@ -98,6 +106,7 @@ template <int BC, int EQ> void fill() {
     f.tin = launch_tin<double, BC, EQ>;
     f.tout = launch_tout<double, BC, EQ>;
     f.rows_per_block = row_block<double, EQ>();
+    if constexpr (wg_step_available<double, L, EQ>()) f.step_wg = launch_step_wg<double, BC, EQ, MODE_F64>;
     // The FCH equation has no mixed-precision form (FP64 only).
     if constexpr (EQ != EQ_FCH) fill_mixed<BC, EQ>();
 }
@@ -116,6 +125,7 @@ template <int BC, int EQ> void fill_mixed() {
     m.tin = launch_tin<float, BC, EQ>;
     m.tout = launch_tout<float, BC, EQ>;
     m.rows_per_block = row_block<float, EQ>();
+    if constexpr (wg_step_available<float, L, EQ>()) m.step_wg = launch_step_wg<float, BC, EQ, MODE_MIXED>;
 }
 
 // ---------------------------------------------------------------- 3-D launchers

@@ -21,6 +21,7 @@ struct KSet {
     launch_fn rowinv = nullptr;     // inverse rows + dual update (T)
     launch_fn upd = nullptr;        // primal update (T)
     launch_fn rowfwd = nullptr;     // FP64: K_ITER64; mixed: K_MIXED (inner or outer pass); no decision
+    launch_fn step_wg = nullptr;    // small grids: the whole step, one workgroup per slot (k_step_wg)
     launch_fn yfwd = nullptr;       // 3-D: forward y-transforms
     launch_fn yfwd_fin = nullptr;   // 3-D: the same, plus the stop decision of the preceding row pass
     launch_fn zsym = nullptr;       // 3-D: forward z-transform, symbol, inverse z-transform

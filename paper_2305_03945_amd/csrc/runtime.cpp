@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -205,6 +206,18 @@ struct Ticket {
 
 struct Traj;
 
+// A batch group's round: its own stream (default priority), so that groups of
+// different shapes overlap on the device and each finishes on its own; the event
+// recorded after the round's work; the trajectories the round advances.  A group
+// has at most one round in flight, and its slot lists are rewritten only when
+// none is.
+struct GroupRound {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool in_flight = false;
+    std::vector<Traj *> trajs;
+};
+
 struct Ctx {
     int device = 0;
     std::map<std::tuple<int, int, uint64_t>, Tables> tables;  // (N, bc, bits of h)
@@ -221,14 +234,9 @@ struct Ctx {
     std::map<uint64_t, Ticket> tickets;
     std::vector<Traj *> trajs;
     std::deque<Traj *> admit_queue;
-    // one stream per concurrently advanced batch group (default priority)
-    std::vector<hipStream_t> serve_streams;
     std::map<std::pair<GroupKey, int>, BatchBuffers> batch;
+    std::map<GroupKey, GroupRound> rounds;
 };
-
-// Batch groups advanced in one pump round run on separate streams, so that
-// groups of different shapes overlap on the device.
-constexpr int SERVE_STREAMS = 4;
 
 struct PendingStep {
     uint64_t ticket;
@@ -508,6 +516,19 @@ rd_status get_step_workspace(Ctx *c, const Desc &d, int mode, Workspace *&out) {
 rd_status run_step(Ctx *c, Workspace &w, const KSet &k, hipStream_t st, int max_iter, int max_outer,
                    double *out = nullptr, size_t nout = 0) {
     Slot *const *slots = w.slot_list_dev;
+    if (k.step_wg) {
+        // small grid: the whole step is one launch
+        k.step_wg(slots, 1, st, nullptr);
+        if (out) launch_copy_out(slots, out, nout, st);
+        RD_CHECK(hipGetLastError());
+        RD_CHECK(hipMemcpyAsync(w.st_host, w.proto.st, sizeof(State), hipMemcpyDeviceToHost, st));
+        RD_CHECK(hipStreamSynchronize(st));
+        remember_step(w, *w.st_host);
+        (void)c;
+        (void)max_iter;
+        (void)max_outer;
+        return RD_OK;
+    }
     k.init(slots, 1, st, nullptr);
     RD_CHECK(hipGetLastError());
     int issued = 0, rounds = 0;
@@ -644,7 +665,10 @@ rd_status rd_destroy(void *ctx) {
             (void)hipFree(kv.second.twd[i]);
         }
     }
-    for (hipStream_t q : c->serve_streams) (void)hipStreamDestroy(q);
+    for (auto &kv : c->rounds) {
+        if (kv.second.stream) (void)hipStreamDestroy(kv.second.stream);
+        if (kv.second.done) (void)hipEventDestroy(kv.second.done);
+    }
     for (auto &kv : c->batch) {
         if (kv.second.dev) (void)hipFree(kv.second.dev);
         if (kv.second.host) (void)hipHostFree(kv.second.host);
@@ -1170,14 +1194,19 @@ rd_status rd_traj_submit(void *traj, double h_t, uint64_t *ticket) {
 
 namespace {
 
-// Serving: one pump round.
-//  1. Admit queued trajectories in arrival order while the resident budget allows.
-//  2. Start the next pending step of every admitted idle trajectory (batched init
-//     launch per key).
-//  3. Advance every running slot by one round of iterations, batched per key
-//     (N, bc, equation family, precision): one launch per kernel for all of them.
-//  4. Read back the states, retire finished steps: copy U^{k+1} to the resident
-//     state, record the ticket's info.
+// Serving.  A pump call:
+//  1. admits queued trajectories in arrival order while the resident budget allows;
+//  2. retires the rounds that have completed: finished steps' tickets get their
+//     info (the results were already copied into the resident states on the
+//     device);
+//  3. starts a round for every group with work and no round in flight: the next
+//     pending step of each idle admitted trajectory (batched initial pass), and
+//     one chunk of iterations for all running slots of the group (one launch per
+//     kernel; small grids run their whole steps in one launch);
+//  4. if no round had completed, waits for the first one that does (at most
+//     max_wait_us when that is > 0), retires it and restarts its group.
+// Groups run on their own streams and finish independently: a short step is not
+// held behind the iterations of another group's long one.
 
 rd_status batch_list(Ctx *c, const GroupKey &key, int role, const std::vector<Traj *> &ts, Slot **&dev,
                      hipStream_t st) {
@@ -1200,40 +1229,47 @@ rd_status batch_list(Ctx *c, const GroupKey &key, int role, const std::vector<Tr
     return RD_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
-    if (!ctx || max_wait_us < 0) return RD_E_INVALID;
-    Ctx *c = (Ctx *)ctx;
-    RD_CHECK(hipSetDevice(c->device));
-    while ((int)c->serve_streams.size() < SERVE_STREAMS) {
-        hipStream_t q = nullptr;
-        RD_CHECK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
-        c->serve_streams.push_back(q);
+// Retire a completed round: record the finished steps' tickets.
+void retire_round(Ctx *c, GroupRound &g) {
+    for (Traj *t : g.trajs) {
+        Workspace &w = *t->ws;
+        const State &s = *w.st_host;
+        const bool fin = w.mode == MODE_F64 ? s.done != 0 : s.outer_done != 0;
+        if (!fin) continue;
+        Ticket &tk = c->tickets[t->running_ticket];
+        info_from_state(s, w.mode, &tk.info);
+        tk.done = true;
+        remember_step(w, s);
+        t->running = false;
     }
+    g.trajs.clear();
+    g.in_flight = false;
+}
+
+// Retire every in-flight round whose work has completed; retired counts them.
+rd_status poll_rounds(Ctx *c, int &retired) {
+    retired = 0;
+    for (auto &kv : c->rounds) {
+        GroupRound &g = kv.second;
+        if (!g.in_flight) continue;
+        const hipError_t e = hipEventQuery(g.done);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return RD_E_DEVICE;
+        retire_round(c, g);
+        ++retired;
+    }
+    return RD_OK;
+}
+
+// Start a round for every batch group that has work and no round in flight.
+rd_status launch_rounds(Ctx *c) {
     rd_status r;
-    // 1. admission, in arrival order, while the resident budget allows
-    while (!c->admit_queue.empty()) {
-        Traj *t = c->admit_queue.front();
-        const size_t need = workspace_bytes(t->d.pts, t->d.rows, t->d.C, t->d.mode,
-                                            kset(t->d.mode, t->d).rows_per_block);
-        if (c->budget && c->resident + need > c->budget && c->resident > 0) break;
-        std::unique_ptr<Workspace> w;
-        r = make_workspace(t->d, t->d.mode, w);
-        if (r == RD_E_NOMEM && c->resident > 0) break;
-        if (r != RD_OK) return r;
-        t->ws = std::move(w);
-        c->resident += need;
-        c->admit_queue.pop_front();
-        t->queued_for_admission = false;
-    }
-    // 2. group admitted trajectories; take the next pending step of idle ones
     std::map<GroupKey, std::vector<Traj *>> starting, running;
     for (Traj *t : c->trajs) {
         if (!t->ws) continue;
         GroupKey key{t->d.mode, t->d.logN, t->d.bc, t->d.eq, t->d.dim};
+        auto gi = c->rounds.find(key);
+        if (gi != c->rounds.end() && gi->second.in_flight) continue;
         if (!t->running && !t->pending.empty()) {
             starting[key].push_back(t);
             running[key].push_back(t);
@@ -1241,15 +1277,14 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
             running[key].push_back(t);
         }
     }
-    // 3. per group, on its own stream: upload the slots of starting steps, one
-    //    batched init launch, one batched round of iterations, state readback
-    std::map<GroupKey, hipStream_t> gstream;
-    int gi = 0;
     for (auto &kv : running) {
         const GroupKey &key = kv.first;
-        hipStream_t st = c->serve_streams[gi++ % SERVE_STREAMS];
-        gstream[key] = st;
+        GroupRound &g = c->rounds[key];
+        if (!g.stream) RD_CHECK(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking));
+        if (!g.done) RD_CHECK(hipEventCreateWithFlags(&g.done, hipEventDisableTiming));
+        hipStream_t st = g.stream;
         const KSet &k = kset(key.mode, kv.second.front()->d);
+        const size_t nfield = (size_t)kv.second.front()->d.C * kv.second.front()->d.pts;
         auto si = starting.find(key);
         if (si != starting.end()) {
             for (Traj *t : si->second) {
@@ -1269,45 +1304,88 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
             }
             Slot **dev = nullptr;
             if ((r = batch_list(c, key, 0, si->second, dev, st)) != RD_OK) return r;
-            k.init(dev, (int)si->second.size(), st, nullptr);
+            if (k.step_wg) {
+                // small grids: the whole steps in one launch, one workgroup each
+                const int n = (int)si->second.size();
+                k.step_wg(dev, n, st, nullptr);
+                launch_copy_back(dev, n, nfield, st);
+            } else {
+                k.init(dev, (int)si->second.size(), st, nullptr);
+            }
             RD_CHECK(hipGetLastError());
         }
-        Slot **dev = nullptr;
-        if ((r = batch_list(c, key, 1, kv.second, dev, st)) != RD_OK) return r;
-        // Round length: the trajectory's previous step predicts this one; a step
-        // that runs longer grows its rounds geometrically (fewer host round trips).
-        // At most 32 iterations: a round ends when its longest group does, so long
-        // steps (Cahn-Hilliard on 1024^2 runs 100-200) would hold the short ones
-        // of every other group back (mixed stream: median step latency about 25 %
-        // lower than with 64, the same throughput; 128 and 256 were worse).
-        int iters = 0;
-        for (Traj *t : kv.second) {
-            const Workspace &w = *t->ws;
-            iters = std::max(iters, std::max(first_chunk(w), t->issued / 2));
+        if (!k.step_wg) {
+            Slot **dev = nullptr;
+            if ((r = batch_list(c, key, 1, kv.second, dev, st)) != RD_OK) return r;
+            // Chunk length: the trajectory's previous step predicts this one; a step
+            // that runs longer grows its chunks geometrically (fewer host round
+            // trips), up to 32 iterations, so that a group's completion is seen soon
+            // enough to start its next steps.
+            int iters = 0;
+            for (Traj *t : kv.second) {
+                const Workspace &w = *t->ws;
+                iters = std::max(iters, std::max(first_chunk(w), t->issued / 2));
+            }
+            iters = std::min(iters, 32);
+            for (Traj *t : kv.second) t->issued += iters;
+            enqueue_round(k, dev, (int)kv.second.size(), iters, st);
+            // steps that finish in this round: U^{k+1} becomes the resident state on
+            // the device, before the host has looked at any State
+            launch_copy_back(dev, (int)kv.second.size(), nfield, st);
+            RD_CHECK(hipGetLastError());
         }
-        iters = std::min(iters, 32);
-        for (Traj *t : kv.second) t->issued += iters;
-        enqueue_round(k, dev, (int)kv.second.size(), iters, st);
-        // steps that finish in this round: U^{k+1} becomes the resident state on the
-        // device, before the host has looked at any State
-        launch_copy_back(dev, (int)kv.second.size(), (size_t)kv.second.front()->d.C * kv.second.front()->d.pts, st);
-        RD_CHECK(hipGetLastError());
         for (Traj *t : kv.second)
             RD_CHECK(hipMemcpyAsync(t->ws->st_host, t->ws->proto.st, sizeof(State), hipMemcpyDeviceToHost, st));
+        RD_CHECK(hipEventRecord(g.done, st));
+        g.trajs = kv.second;
+        g.in_flight = true;
     }
-    for (auto &kv : gstream) RD_CHECK(hipStreamSynchronize(kv.second));
-    // 4. retire finished steps (their results are already resident)
-    for (auto &kv : running) {
-        for (Traj *t : kv.second) {
-            Workspace &w = *t->ws;
-            const State &s = *w.st_host;
-            const bool fin = w.mode == MODE_F64 ? s.done != 0 : s.outer_done != 0;
-            if (!fin) continue;
-            Ticket &tk = c->tickets[t->running_ticket];
-            info_from_state(s, w.mode, &tk.info);
-            tk.done = true;
-            remember_step(w, s);
-            t->running = false;
+    return RD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
+    if (!ctx || max_wait_us < 0) return RD_E_INVALID;
+    Ctx *c = (Ctx *)ctx;
+    RD_CHECK(hipSetDevice(c->device));
+    rd_status r;
+    // 1. admission, in arrival order, while the resident budget allows
+    while (!c->admit_queue.empty()) {
+        Traj *t = c->admit_queue.front();
+        const size_t need = workspace_bytes(t->d.pts, t->d.rows, t->d.C, t->d.mode,
+                                            kset(t->d.mode, t->d).rows_per_block);
+        if (c->budget && c->resident + need > c->budget && c->resident > 0) break;
+        std::unique_ptr<Workspace> w;
+        r = make_workspace(t->d, t->d.mode, w);
+        if (r == RD_E_NOMEM && c->resident > 0) break;
+        if (r != RD_OK) return r;
+        t->ws = std::move(w);
+        c->resident += need;
+        c->admit_queue.pop_front();
+        t->queued_for_admission = false;
+    }
+    // 2. retire completed rounds, 3. start rounds for idle groups
+    int retired = 0;
+    if ((r = poll_rounds(c, retired)) != RD_OK) return r;
+    if ((r = launch_rounds(c)) != RD_OK) return r;
+    // 4. wait for the first completion, then restart that group
+    if (retired == 0) {
+        bool any = false;
+        for (auto &kv : c->rounds) any = any || kv.second.in_flight;
+        if (any) {
+            const auto t0 = std::chrono::steady_clock::now();
+            while (true) {
+                if ((r = poll_rounds(c, retired)) != RD_OK) return r;
+                if (retired > 0) break;
+                if (max_wait_us > 0 && std::chrono::duration_cast<std::chrono::microseconds>(
+                                           std::chrono::steady_clock::now() - t0).count() >= max_wait_us)
+                    break;
+                std::this_thread::yield();
+            }
+            if (retired > 0 && (r = launch_rounds(c)) != RD_OK) return r;
         }
     }
     return RD_OK;
@@ -1354,6 +1432,9 @@ rd_status rd_traj_close(void *traj) {
     Ctx *c = t->ctx;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
+    // every round has completed: retire them, so that none refers to t afterwards
+    for (auto &kv : c->rounds)
+        if (kv.second.in_flight) retire_round(c, kv.second);
     if (t->ws) {
         c->resident -= std::min(c->resident, t->ws->bytes);
         free_workspace(t->ws.get());

@@ -168,6 +168,21 @@ template <int KIND> void f_fin(Slot *const *slots, int nslots, hipStream_t, hipE
     }
 }
 
+// The whole step in one launch (the device's k_step_wg): the same launches in
+// order until every slot has finished.
+template <int MODE> void f_step_wg(Slot *const *slots, int nslots, hipStream_t st, hipEvent_t *) {
+    constexpr int KIT = MODE == MODE_F64 ? K_ITER64 : K_MIXED;
+    f_init<MODE, MODE == MODE_F64 ? K_INIT64 : K_OUTER_INIT>(slots, nslots, st, nullptr);
+    for (int guard = 0; guard < 1000000; ++guard) {
+        bool all = true;
+        for (int i = 0; i < nslots; ++i) all = all && slots[i]->st->outer_done;
+        if (all) break;
+        f_upd<MODE>(slots, nslots, st, nullptr);
+        f_rowfwd<MODE>(slots, nslots, st, nullptr);
+        f_fin<KIT>(slots, nslots, st, nullptr);
+    }
+}
+
 void f_tin(Slot *const *, int, const double *, double *, hipStream_t) {}
 void f_tout(Slot *const *, int, const double *, double *, hipStream_t) {}
 
@@ -196,6 +211,9 @@ void fill(int L) {
                 k.tout = f_tout;
                 k.rows_per_block = 2;
                 k.dim = 2;
+                // small grids (N <= 32 here) take the single-launch step
+                if (L <= 5 && eq != EQ_FCH)
+                    k.step_wg = mode == MODE_F64 ? f_step_wg<MODE_F64> : f_step_wg<MODE_MIXED>;
             }
 }
 

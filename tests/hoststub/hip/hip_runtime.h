@@ -10,7 +10,7 @@
 #include <cstring>
 
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2, hipErrorNotReady = 600 };
 enum hipMemcpyKind { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
                      hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 };
 struct ihipStream_t { int id; };
@@ -19,6 +19,7 @@ typedef ihipStream_t *hipStream_t;
 typedef ihipEvent_t *hipEvent_t;
 constexpr unsigned hipHostMallocDefault = 0;
 constexpr unsigned hipStreamNonBlocking = 1;
+constexpr unsigned hipEventDisableTiming = 2;
 
 namespace hipstub {
 // Live allocations (device and pinned), events and streams: a test checks that a
@@ -65,4 +66,12 @@ inline hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
 inline hipError_t hipStreamDestroy(hipStream_t s) { delete s; --hipstub::live_streams(); return hipSuccess; }
 inline hipError_t hipEventCreate(hipEvent_t *e) { *e = new ihipEvent_t{0}; return hipSuccess; }
 inline hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
+inline hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { return hipEventCreate(e); }
+// Work is done when it is enqueued; a query still reports "not ready" two times in
+// three, so that callers' waiting paths run.
+inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+inline hipError_t hipEventQuery(hipEvent_t) {
+    static unsigned n = 0;
+    return (n++ % 3 == 2) ? hipSuccess : hipErrorNotReady;
+}
 inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) { *ms = 0.f; return hipSuccess; }

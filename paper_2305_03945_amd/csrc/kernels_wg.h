@@ -7,8 +7,8 @@
 //
 //   W = F(U_n) (stencil)  -> spectrum S in LDS (row pairs packed as complex rows)
 //   ||W / h_t|| (fixed-order workgroup sum), stop decision (decide<>, thread 0)
-//   row FFTs, transpose to columns, column FFTs, 1 / (N^2 g), inverse column
-//   FFTs, transpose back, inverse row FFTs          -> Y = G^-1 W_n in LDS
+//   row FFTs, column FFTs (on the row layout), 1 / (N^2 g), inverse column
+//   FFTs, inverse row FFTs                          -> Y = G^-1 W_n in LDS
 //   P_{n+1} = P_n + tau_p Y,  P~ = P_{n+1} + omega tau_p Y (P~ kept in LDS)
 //   U_{n+1} = U_n - tau_u grad F(U_n)^T P~
 //
@@ -18,7 +18,8 @@
 // and r take LDS in that order while the 160 KB of a gfx950 workgroup allow, and
 // otherwise stay in the slot's HBM buffers (then L2-resident).  The arithmetic
 // per point is that of the batched kernels (the same eval_F / eval_Ftilde /
-// eval_adjoint / transform code); only the order of the norm's sums differs.
+// eval_adjoint code, the pair / cosine processing and symbol of fft.h); the
+// transforms are radix-8 passes and the norm's sums run in another order.
 #pragma once
 #include "kernels.h"
 
@@ -89,8 +90,8 @@ template <int K> __device__ __forceinline__ void wg_sum(double *v, double *red) 
 // packed per LDS region): element i of column job reg (component c = reg / H,
 // column kx = reg % H) is row y of that column, y = i on periodic grids and the
 // row whose Makhoul position is i on Neumann grids, at slot (y & 1) H + kx of
-// region c H + y / 2.  The Stockham passes of fft16.h with that address map, so
-// no transpose is needed between the row and the column transforms.
+// region c H + y / 2.  The transforms below take an address map, so no transpose
+// is needed between the row and the column transforms.
 template <int LOGN, int BC> struct ColMap {
     static constexpr int N = 1 << LOGN, H = N / 2;
     __device__ __forceinline__ static int row_of(int i) {
@@ -103,37 +104,57 @@ template <int LOGN, int BC> struct ColMap {
     }
 };
 
-template <typename T, int LOGN, int R, int NS, int DIR, class M>
-__device__ __forceinline__ void mpass16(cplx<T> *buf, int reg, int t, bool active, const cplx<T> (*pw)[4]) {
-    constexpr int N = 1 << LOGN;
-    constexpr int TPF = N / 16;
-    constexpr int NB = N / R;
-    constexpr int BPT = 16 / R;
+// ---------------------------------------------------------------- radix-8 transforms
+// The single-workgroup step's transforms (N <= 64): Stockham passes of radix 8 while
+// three bits remain, then one of radix 4 or 2, with 8 values per thread (N/8 threads
+// per transform: twice the threads of the radix-16 passes on these short
+// transforms, whose passes are bound by arithmetic latency, not LDS).  Pass q reads
+// element j + r N/R of butterfly j, multiplies input r by W_{NS R}^{r k} (k = j mod
+// NS), applies DFT_R and writes output q to (j - k) R + k + q NS.  The twiddles of a
+// thread depend only on its index in its team, so they are read from the table
+// exp(-2 pi i m / N) once per step and kept in registers; the inverse conjugates.
+template <int LOGN> constexpr int r8_radix(int q) { return LOGN - 3 * q >= 3 ? 8 : (1 << (LOGN - 3 * q)); }
+template <int LOGN> constexpr int r8_passes() { return (LOGN + 2) / 3; }
+
+template <typename T, int LOGN> struct TwR8 {
+    // pass 1 (the only pass with NS > 1 for N <= 64): butterflies b < 8 / R, inputs 1..R-1
+    cplx<T> w[4][7];
+};
+
+template <typename T, int LOGN>
+__device__ __forceinline__ void load_twr8(TwR8<T, LOGN> &tw, const cplx<T> *table) {
+    static_assert(r8_passes<LOGN>() <= 2, "radix-8 step transforms: N <= 64");
+    constexpr int N = 1 << LOGN, TPT = N / 8;
+    if constexpr (r8_passes<LOGN>() == 2) {
+        constexpr int R = r8_radix<LOGN>(1), NS = 8, NB = N / R, BPT = 8 / R;
+        constexpr int STEP = N / (NS * R);
+        const int t = threadIdx.x % TPT;
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) {
+            const int j = t + b * TPT;
+            const int k = j & (NS - 1);
+            (void)NB;
+#pragma unroll
+            for (int r = 1; r < R; ++r) tw.w[b][r - 1] = table[(r * k * STEP) & (N - 1)];
+        }
+    }
+}
+
+template <typename T, int LOGN, int Q, int DIR, class M>
+__device__ __forceinline__ void r8_pass(cplx<T> *buf, int reg, int t, bool active, const TwR8<T, LOGN> &tw) {
+    constexpr int N = 1 << LOGN, TPT = N / 8;
+    constexpr int R = r8_radix<LOGN>(Q), NS = Q == 0 ? 1 : 8, NB = N / R, BPT = 8 / R;
     cplx<T> v[BPT][R];
     if (active) {
 #pragma unroll
         for (int b = 0; b < BPT; ++b) {
-            const int j = t + b * TPF;
+            const int j = t + b * TPT;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b][r] = buf[M::at(reg, j + r * NB)];
             if constexpr (NS > 1) {
-                cplx<T> p[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if ((1 << e) < R) {
-                        p[e] = pw[b][e];
-                        if constexpr (DIR > 0) p[e].im = -p[e].im;
-                    }
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    cplx<T> w = {(T)1, (T)0};
-                    bool first = true;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (r & (1 << e)) {
-                            w = first ? p[e] : cmul(w, p[e]);
-                            first = false;
-                        }
+                    const cplx<T> w = DIR < 0 ? tw.w[b][r - 1] : cconj(tw.w[b][r - 1]);
                     v[b][r] = cmul(v[b][r], w);
                 }
             }
@@ -144,7 +165,7 @@ __device__ __forceinline__ void mpass16(cplx<T> *buf, int reg, int t, bool activ
     if (active) {
 #pragma unroll
         for (int b = 0; b < BPT; ++b) {
-            const int j = t + b * TPF;
+            const int j = t + b * TPT;
             const int k = j & (NS - 1);
             const int base = (j - k) * R + k;
 #pragma unroll
@@ -154,32 +175,25 @@ __device__ __forceinline__ void mpass16(cplx<T> *buf, int reg, int t, bool activ
     __syncthreads();
 }
 
-template <typename T, int LOGN, int DIR, int DONE, class M>
-__device__ __forceinline__ void mpasses16(cplx<T> *buf, int reg, int t, bool active, const Tw16<T, LOGN> &w) {
-    if constexpr (DONE < LOGN) {
-        constexpr int REM = LOGN - DONE;
-        constexpr int R = REM >= 4 ? 16 : (1 << REM);
-        constexpr int LOGR = REM >= 4 ? 4 : REM;
-        constexpr int q = DONE / 4;
-        mpass16<T, LOGN, R, (1 << DONE), DIR, M>(buf, reg, t, active, w.p[q > 0 ? q - 1 : 0]);
-        mpasses16<T, LOGN, DIR, DONE + LOGR, M>(buf, reg, t, active, w);
-    }
-}
-
-// In-place transforms of NREG mapped regions by NTH threads (teams of N/16 take
-// regions round-robin); ends with a barrier.
+// In-place transforms of NREG regions (address map M) by NTH threads; teams of N/8
+// threads take regions round-robin.  Ends with a barrier.
 template <typename T, int LOGN, int DIR, int NREG, int NTH, class M>
-__device__ __forceinline__ void wg_fft16_mapped(cplx<T> *buf, const Tw16<T, LOGN> &w) {
-    constexpr int TPF = (1 << LOGN) / 16;
-    constexpr int NTEAMS = NTH / TPF;
-    const int team = threadIdx.x / TPF, t = threadIdx.x % TPF;
+__device__ __forceinline__ void wg_fft_r8(cplx<T> *buf, const TwR8<T, LOGN> &tw) {
+    constexpr int TPT = (1 << LOGN) / 8;
+    constexpr int NTEAMS = NTH / TPT;
+    const int team = threadIdx.x / TPT, t = threadIdx.x % TPT;
 #pragma unroll 1
     for (int g = 0; g < NREG; g += NTEAMS) {
         const int reg = g + team;
         const bool active = reg < NREG;
-        mpasses16<T, LOGN, DIR, 0, M>(buf, active ? reg : 0, t, active, w);
+        r8_pass<T, LOGN, 0, DIR, M>(buf, active ? reg : 0, t, active, tw);
+        if constexpr (r8_passes<LOGN>() == 2) r8_pass<T, LOGN, 1, DIR, M>(buf, active ? reg : 0, t, active, tw);
     }
 }
+
+template <int LOGN> struct RowMap {
+    __device__ __forceinline__ static int at(int reg, int i) { return rix<LOGN>(reg, i); }
+};
 
 // 1 / (N^2 g) on the transformed columns (cols_apply_symbol of fft.h on the
 // mapped layout): column job reg of component c = reg / H is kx = reg % H
@@ -246,35 +260,22 @@ __device__ __forceinline__ void cols_symbol_mapped(cplx<T> *buf, SlotRef s, cons
     __syncthreads();
 }
 
-// Stencil offsets of reach HY (0: the point; 1: the 5-point stencil; 2: the
-// 13-point one) and the slot of (dy, dx) in that list: the point phases gather a
-// chunk of points' neighbourhoods into registers before they compute and store, so
-// that their loads are not held behind stores to memory they might alias.
-template <int HY> struct Stencil {
-    static constexpr int NS = HY == 0 ? 1 : (HY == 1 ? 5 : 13);
-    __device__ __forceinline__ static constexpr int dy(int i) {
-        constexpr int t[13] = {0, 0, 0, -1, 1, -1, -1, 1, 1, 0, 0, -2, 2};
-        return t[i];
-    }
-    __device__ __forceinline__ static constexpr int dx(int i) {
-        constexpr int t[13] = {0, -1, 1, 0, 0, -1, 1, -1, 1, -2, 2, 0, 0};
-        return t[i];
-    }
-    __device__ __forceinline__ static constexpr int idx(int y, int x) {
-        for (int i = 0; i < 13; ++i)
-            if (dy(i) == y && dx(i) == x) return i;
-        return 0;
-    }
-};
-
-// Points per thread, and per chunk of a point phase gathering G values of B bytes
-// per point (about 160 bytes of gathered values per thread, within the register
-// budget of a 512-thread workgroup).
-template <int LOGN> constexpr int wg_ppt() { return (1 << (2 * LOGN)) >= NT7 ? (1 << (2 * LOGN)) / NT7 : 1; }
-template <int LOGN, int G, int B> constexpr int wg_chunk() {
-    constexpr int c = 160 / (G * B) < 1 ? 1 : 160 / (G * B);
-    constexpr int ppt = wg_ppt<LOGN>();
-    return c >= ppt ? ppt : (c >= 8 ? 8 : c >= 4 ? 4 : c >= 2 ? 2 : 1);
+// Strips: in the point phases thread t takes rows y0 .. y0 + L - 1 of column
+// x = t mod N (L = N^2 / NT7, at least 1), in sub-strips of LS rows whose stencil
+// neighbourhood (reach HY, the diamond |dy| + |dx| <= HY: 5 or 13 points) it loads
+// into registers once.  The rows of a sub-strip pair up (2q, 2q + 1), the two rows
+// a complex slot of the spectrum packs, so W and Y move as one complex value.
+template <int LOGN> constexpr int wg_strip() { return (1 << (2 * LOGN)) >= NT7 ? (1 << (2 * LOGN)) / NT7 : 1; }
+template <int LOGN, int HY, int C> constexpr int wg_substrip() {
+    constexpr int L = wg_strip<LOGN>();
+    constexpr int cap = (HY >= 2 || C == 2) ? 2 : 8;   // windows within the register budget
+    return L < cap ? L : cap;
+}
+// Whether window row r (-HY .. LS - 1 + HY) at column offset dx is in the
+// neighbourhood of some row of a sub-strip of LS rows.
+template <int HY, int LS> __host__ __device__ constexpr bool wg_needed(int r, int dx) {
+    const int dist = r < 0 ? -r : (r >= LS ? r - LS + 1 : 0);
+    return dist + (dx < 0 ? -dx : dx) <= HY;
 }
 
 template <typename T, int LOGN, int BC, int EQ, int MODE>
@@ -285,9 +286,6 @@ __global__ __launch_bounds__(NT7) void k_step_wg(Slot *const *slots) {
     constexpr int NREG = C * H;   // row-pair regions = column regions
     constexpr int HY = stencil_hy<EQ>();
     constexpr int HU = EQ == EQ_BIH ? 1 : 0;   // reach of U in the mixed inner residual
-    using SY = Stencil<HY>;
-    using SU = Stencil<HU>;
-    constexpr int PPT = wg_ppt<LOGN>();
     using Plan = WgPlan<T, LOGN, C>;
     static_assert(Plan::ok, "the spectrum must fit in LDS");
     static_assert(MODE == MODE_F64 ? sizeof(T) == 8 : sizeof(T) == 4, "FP64 step or FP32 inner loop");
@@ -313,12 +311,25 @@ __global__ __launch_bounds__(NT7) void k_step_wg(Slot *const *slots) {
     const double *src = s.src;     // U^k: the caller's input, read-only for the whole step
     const double *Ukp = Plan::uk_lds ? (const double *)nxt : src;
     double *U64 = s.U64[0];        // mixed: FP64 U (never bound to the caller's input)
-    Tw16<T, LOGN> twr;
-    load_tw16<T, LOGN>(twr, (const cplx<T> *)s.tw);
+    TwR8<T, LOGN> twr;
+    load_twr8<T, LOGN>(twr, (const cplx<T> *)s.tw);
     const StopRule rule{s.tol, s.inner_rtol, s.max_iter, s.max_outer};
     auto pos = [](int x) { return BC == BC_P ? x : dct_pos(x, N); };
     auto at = [](int c, int y, int x) { return c * NN + wrap<BC>(y, N) * N + wrap<BC>(x, N); };
-    auto pt_of = [&](int i) { return tid + i * NT7; };
+    constexpr int L = wg_strip<LOGN>();
+    constexpr int LS = wg_substrip<LOGN, HY, C>();
+    constexpr int STRIP_THREADS = N * (N / L);
+    static_assert(L % LS == 0 && (LS == 1 || LS % 2 == 0), "sub-strips of whole row pairs");
+    // W of rows ys .. ys + LS - 1 at column x into the spectrum's row-pair layout
+    auto store_w = [&](int c, int ys, int x, const double *W) {
+        if constexpr (LS >= 2) {
+#pragma unroll
+            for (int q = 0; q < LS / 2; ++q)
+                S[rix<LOGN>(c * H + (ys >> 1) + q, pos(x))] = cplx<T>{(T)W[2 * q], (T)W[2 * q + 1]};
+        } else {
+            rreal<T, LOGN>(S, c * H + ys / 2, 2 * pos(x) + (ys & 1)) = (T)W[0];
+        }
+    };
     if (tid == 0) stl = State{};
     for (int i = tid; i < N; i += NT7) {
         eig_l[i] = s.eig[i];
@@ -331,42 +342,46 @@ __global__ __launch_bounds__(NT7) void k_step_wg(Slot *const *slots) {
     // ---- the residual of an FP64 state (U_0, or the mixed outer U) into S; its
     // norm and sum(U - U^k) decided by thread 0
     auto residual64 = [&](const double *Uf, auto decide_fn) {
-        constexpr int CK = wg_chunk<LOGN, C *(SY::NS + 1), 8>();
         double acc[2 * C];
 #pragma unroll
         for (int k = 0; k < 2 * C; ++k) acc[k] = 0.0;
+        if (tid < STRIP_THREADS) {
+            const int x = tid % N, y0 = (tid / N) * L;
 #pragma unroll 1
-        for (int i0 = 0; i0 < PPT; i0 += CK) {
-            double v[CK][C][SY::NS], uk[CK][C];
-#pragma unroll
-            for (int j = 0; j < CK; ++j) {
-                const int g = pt_of(i0 + j);
-                if (g >= NN) continue;
-                const int y = g >> LOGN, x = g & (N - 1);
+            for (int s0 = 0; s0 < L; s0 += LS) {
+                const int ys = y0 + s0;
+                double v[C][LS + 2 * HY][2 * HY + 1], uk[C][LS];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    uk[j][c] = Ukp[c * NN + g];
 #pragma unroll
-                    for (int q = 0; q < SY::NS; ++q) v[j][c][q] = Uf[at(c, y + SY::dy(q), x + SY::dx(q))];
+                    for (int r = -HY; r < LS + HY; ++r)
+#pragma unroll
+                        for (int dx = -HY; dx <= HY; ++dx)
+                            if (wg_needed<HY, LS>(r, dx)) v[c][r + HY][dx + HY] = Uf[at(c, ys + r, x + dx)];
+#pragma unroll
+                    for (int i = 0; i < LS; ++i) uk[c][i] = Ukp[c * NN + (ys + i) * N + x];
                 }
-            }
+                double W[C][LS];
 #pragma unroll
-            for (int j = 0; j < CK; ++j) {
-                const int g = pt_of(i0 + j);
-                if (g >= NN) continue;
-                const int y = g >> LOGN, x = g & (N - 1);
-                double W[C], Uc[C];
-                eval_F<EQ, double>(s, [&](int c, int dy, int dx) { return v[j][c][SY::idx(dy, dx)]; }, uk[j], W, Uc);
+                for (int i = 0; i < LS; ++i) {
+                    double Wi[C], Uc[C], ukc[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    acc[c] += W[c] * W[c];
-                    acc[C + c] += Uc[c] - uk[j][c];
-                    if constexpr (MODE == MODE_MIXED) {
-                        Rr[c * NN + g] = (float)W[c];
-                        Ub[c * NN + g] = (float)Uc[c];
+                    for (int c = 0; c < C; ++c) ukc[c] = uk[c][i];
+                    eval_F<EQ, double>(s, [&](int c, int dy, int dx) { return v[c][i + dy + HY][dx + HY]; }, ukc, Wi,
+                                       Uc);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        W[c][i] = Wi[c];
+                        acc[c] += Wi[c] * Wi[c];
+                        acc[C + c] += Uc[c] - ukc[c];
+                        if constexpr (MODE == MODE_MIXED) {
+                            Rr[c * NN + (ys + i) * N + x] = (float)Wi[c];
+                            Ub[c * NN + (ys + i) * N + x] = (float)Uc[c];
+                        }
                     }
-                    rreal<T, LOGN>(S, c * H + y / 2, 2 * pos(x) + (y & 1)) = (T)W[c];
                 }
+#pragma unroll
+                for (int c = 0; c < C; ++c) store_w(c, ys, x, W[c]);
             }
         }
         wg_sum<2 * C>(acc, red);
@@ -384,40 +399,46 @@ __global__ __launch_bounds__(NT7) void k_step_wg(Slot *const *slots) {
 
     // ---- the mixed inner residual F~(e) into S; its norm decided by thread 0
     auto residual32 = [&]() {
-        constexpr int CK = wg_chunk<LOGN, C *(SY::NS + SU::NS + 1), 4>();
         double acc[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = 0.0;
+        if (tid < STRIP_THREADS) {
+            const int x = tid % N, y0 = (tid / N) * L;
 #pragma unroll 1
-        for (int i0 = 0; i0 < PPT; i0 += CK) {
-            float ve[CK][C][SY::NS], vu[CK][C][SU::NS], rc[CK][C];
-#pragma unroll
-            for (int j = 0; j < CK; ++j) {
-                const int g = pt_of(i0 + j);
-                if (g >= NN) continue;
-                const int y = g >> LOGN, x = g & (N - 1);
+            for (int s0 = 0; s0 < L; s0 += LS) {
+                const int ys = y0 + s0;
+                float ve[C][LS + 2 * HY][2 * HY + 1], vu[C][LS + 2 * HU][2 * HU + 1], rc[C][LS];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    rc[j][c] = Rr[c * NN + g];
 #pragma unroll
-                    for (int q = 0; q < SY::NS; ++q) ve[j][c][q] = (float)U[at(c, y + SY::dy(q), x + SY::dx(q))];
+                    for (int r = -HY; r < LS + HY; ++r)
 #pragma unroll
-                    for (int q = 0; q < SU::NS; ++q) vu[j][c][q] = Ub[at(c, y + SU::dy(q), x + SU::dx(q))];
+                        for (int dx = -HY; dx <= HY; ++dx)
+                            if (wg_needed<HY, LS>(r, dx)) ve[c][r + HY][dx + HY] = (float)U[at(c, ys + r, x + dx)];
+#pragma unroll
+                    for (int r = -HU; r < LS + HU; ++r)
+#pragma unroll
+                        for (int dx = -HU; dx <= HU; ++dx)
+                            if (wg_needed<HU, LS>(r, dx)) vu[c][r + HU][dx + HU] = Ub[at(c, ys + r, x + dx)];
+#pragma unroll
+                    for (int i = 0; i < LS; ++i) rc[c][i] = Rr[c * NN + (ys + i) * N + x];
                 }
-            }
+                double W[C][LS];
 #pragma unroll
-            for (int j = 0; j < CK; ++j) {
-                const int g = pt_of(i0 + j);
-                if (g >= NN) continue;
-                const int y = g >> LOGN, x = g & (N - 1);
-                float W[C];
-                eval_Ftilde<EQ>(s, [&](int c, int dy, int dx) { return ve[j][c][SY::idx(dy, dx)]; },
-                                [&](int c, int dy, int dx) { return vu[j][c][SU::idx(dy, dx)]; }, rc[j], W);
+                for (int i = 0; i < LS; ++i) {
+                    float Wi[C], r[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    acc[c] += (double)W[c] * (double)W[c];
-                    rreal<T, LOGN>(S, c * H + y / 2, 2 * pos(x) + (y & 1)) = (T)W[c];
+                    for (int c = 0; c < C; ++c) r[c] = rc[c][i];
+                    eval_Ftilde<EQ>(s, [&](int c, int dy, int dx) { return ve[c][i + dy + HY][dx + HY]; },
+                                    [&](int c, int dy, int dx) { return vu[c][i + dy + HU][dx + HU]; }, r, Wi);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        W[c][i] = Wi[c];
+                        acc[c] += (double)Wi[c] * (double)Wi[c];
+                    }
                 }
+#pragma unroll
+                for (int c = 0; c < C; ++c) store_w(c, ys, x, W[c]);
             }
         }
         wg_sum<C>(acc, red);
@@ -433,13 +454,13 @@ __global__ __launch_bounds__(NT7) void k_step_wg(Slot *const *slots) {
     // ---- Y = G^-1 W in place (W in S as packed row pairs on entry; on exit the
     // complex slot pos(x) of region c H + y / 2 holds Y of rows y, y + 1 as re, im)
     auto precond = [&]() {
-        wg_fft16<T, LOGN, -1, NREG, NT7>(S, twr);
+        wg_fft_r8<T, LOGN, -1, NREG, NT7, RowMap<LOGN>>(S, twr);
         rows_post_forward<T, LOGN, BC, NREG, NT7>(S, twd);
-        wg_fft16_mapped<T, LOGN, -1, NREG, NT7, ColMap<LOGN, BC>>(S, twr);
+        wg_fft_r8<T, LOGN, -1, NREG, NT7, ColMap<LOGN, BC>>(S, twr);
         cols_symbol_mapped<T, LOGN, BC, NREG, NT7, ColMap<LOGN, BC>>(S, s, eig_l, twd);
-        wg_fft16_mapped<T, LOGN, +1, NREG, NT7, ColMap<LOGN, BC>>(S, twr);
+        wg_fft_r8<T, LOGN, +1, NREG, NT7, ColMap<LOGN, BC>>(S, twr);
         rows_pre_inverse<T, LOGN, BC, NREG, NT7>(S, twd);
-        wg_fft16<T, LOGN, +1, NREG, NT7>(S, twr);
+        wg_fft_r8<T, LOGN, +1, NREG, NT7, RowMap<LOGN>>(S, twr);
     };
     auto Yat = [&](int c, int y, int x) -> T {
         const cplx<T> zv = S[rix<LOGN>(c * H + (y >> 1), pos(x))];
@@ -447,74 +468,83 @@ __global__ __launch_bounds__(NT7) void k_step_wg(Slot *const *slots) {
     };
 
     // ---- primal descent U_{n+1} = U_n - tau_u grad F(U_n)^T P~ with
-    // P~ = P_{n+1} + omega (P_{n+1} - P_n), P_{n+1} = P_n + tau_p Y, formed where the
-    // stencil reads it, in place on U (the adjoint reads U only at its own point);
-    // mixed: on e, with f' at U_b + e.  Then the dual ascent P_{n+1} = P_n + tau_p Y,
-    // once every thread has read the P_n it needs.
+    // P~ = P_{n+1} + omega (P_{n+1} - P_n), P_{n+1} = P_n + tau_p Y, formed in the
+    // registers of the strip that reads it, in place on U (the adjoint reads U only
+    // at its own point); mixed: on e, with f' at U_b + e.  Then the dual ascent:
+    // P_{n+1} of the strip's own points, stored once every thread has read the P_n
+    // it needs.
     auto primal_dual = [&](bool first) {
         const T tu = (T)s.tau_u, tp = (T)s.tau_p, om = (T)s.omega;
-        constexpr int CK = wg_chunk<LOGN, C *(SY::NS + 2), (int)sizeof(T)>();
-#pragma unroll 1
-        for (int i0 = 0; i0 < PPT; i0 += CK) {
-            T pt[CK][C][SY::NS], un[CK][C], Uc[CK][C];
+        T pnew[C][L];
+        if (tid < STRIP_THREADS) {
+            const int x = tid % N, y0 = (tid / N) * L;
 #pragma unroll
-            for (int j = 0; j < CK; ++j) {
-                const int g = pt_of(i0 + j);
-                if (g >= NN) continue;
-                const int y = g >> LOGN, x = g & (N - 1);
+            for (int s0 = 0; s0 < L; s0 += LS) {
+                const int ys = y0 + s0;
+                T pt[C][LS + 2 * HY][2 * HY + 1];
+                auto cell = [&](int c, int r, int dx, int yy, int xx, T Y) {
+                    const T pn = first ? (T)0 : P[c * NN + yy * N + xx];
+                    const T pn1 = pn + tp * Y;
+                    pt[c][r + HY][dx + HY] = pn1 + om * (pn1 - pn);
+                    if (dx == 0 && r >= 0 && r < LS) pnew[c][s0 + r] = pn1;
+                };
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    if constexpr (MODE == MODE_F64) {
-                        un[j][c] = U[c * NN + g];
-                        Uc[j][c] = un[j][c];
-                    } else {
-                        un[j][c] = first ? (T)0 : U[c * NN + g];
-                        Uc[j][c] = (T)Ub[c * NN + g] + un[j][c];
+                for (int c = 0; c < C; ++c)
+#pragma unroll
+                    for (int dx = -HY; dx <= HY; ++dx) {
+                        const int xx = wrap<BC>(x + dx, N), px = pos(xx);
+                        if constexpr (LS >= 2) {
+                            // the strip's own rows, two per complex slot
+#pragma unroll
+                            for (int q = 0; q < LS / 2; ++q) {
+                                const cplx<T> z = S[rix<LOGN>(c * H + (ys >> 1) + q, px)];
+                                cell(c, 2 * q, dx, ys + 2 * q, xx, z.re);
+                                cell(c, 2 * q + 1, dx, ys + 2 * q + 1, xx, z.im);
+                            }
+                        } else {
+                            const cplx<T> z = S[rix<LOGN>(c * H + (ys >> 1), px)];
+                            cell(c, 0, dx, ys, xx, (ys & 1) ? z.im : z.re);
+                        }
+                        // halo rows, through the boundary map
+#pragma unroll
+                        for (int r = -HY; r < LS + HY; ++r) {
+                            if (r >= 0 && r < LS) continue;
+                            if (!wg_needed<HY, LS>(r, dx)) continue;
+                            const int yy = wrap<BC>(ys + r, N);
+                            const cplx<T> z = S[rix<LOGN>(c * H + (yy >> 1), px)];
+                            cell(c, r, dx, yy, xx, (yy & 1) ? z.im : z.re);
+                        }
                     }
 #pragma unroll
-                    for (int q = 0; q < SY::NS; ++q) {
-                        const int yy = wrap<BC>(y + SY::dy(q), N), xx = wrap<BC>(x + SY::dx(q), N);
-                        const T pn = first ? (T)0 : P[c * NN + yy * N + xx];
-                        const T pn1 = pn + tp * Yat(c, yy, xx);
-                        pt[j][c][q] = pn1 + om * (pn1 - pn);
+                for (int i = 0; i < LS; ++i) {
+                    const int g = (ys + i) * N + x;
+                    T un[C], Uc[C], adj[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        if constexpr (MODE == MODE_F64) {
+                            un[c] = U[c * NN + g];
+                            Uc[c] = un[c];
+                        } else {
+                            un[c] = first ? (T)0 : U[c * NN + g];
+                            Uc[c] = (T)Ub[c * NN + g] + un[c];
+                        }
                     }
+                    eval_adjoint<EQ, T>(s, [&](int c, int dy, int dx) { return pt[c][i + dy + HY][dx + HY]; }, Uc,
+                                        adj);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) U[c * NN + g] = un[c] - tu * adj[c];
                 }
-            }
-#pragma unroll
-            for (int j = 0; j < CK; ++j) {
-                const int g = pt_of(i0 + j);
-                if (g >= NN) continue;
-                T adj[C];
-                eval_adjoint<EQ, T>(s, [&](int c, int dy, int dx) { return pt[j][c][SY::idx(dy, dx)]; }, Uc[j], adj);
-#pragma unroll
-                for (int c = 0; c < C; ++c) U[c * NN + g] = un[j][c] - tu * adj[c];
             }
         }
         __syncthreads();
-        constexpr int CKP = wg_chunk<LOGN, 2 * C, (int)sizeof(T)>();
-#pragma unroll 1
-        for (int i0 = 0; i0 < PPT; i0 += CKP) {
-            T pn[CKP][C], yv[CKP][C];
+        if (tid < STRIP_THREADS) {
+            const int x = tid % N, y0 = (tid / N) * L;
 #pragma unroll
-            for (int j = 0; j < CKP; ++j) {
-                const int g = pt_of(i0 + j);
-                if (g >= NN) continue;
-                const int y = g >> LOGN, x = g & (N - 1);
+            for (int c = 0; c < C; ++c)
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    pn[j][c] = first ? (T)0 : P[c * NN + g];
-                    yv[j][c] = Yat(c, y, x);
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < CKP; ++j) {
-                const int g = pt_of(i0 + j);
-                if (g >= NN) continue;
-#pragma unroll
-                for (int c = 0; c < C; ++c) P[c * NN + g] = pn[j][c] + tp * yv[j][c];
-            }
+                for (int i = 0; i < L; ++i) P[c * NN + (y0 + i) * N + x] = pnew[c][i];
         }
-        __syncthreads();
+        // the next reader of P is the next primal step, several barriers later
     };
 
     // ---- the initial state U_0 = U^k (or the pointwise reaction prox of U^k)

@@ -50,6 +50,37 @@ __device__ __forceinline__ double prox_ac(double c, double ht, double b) {
     }
     return u;
 }
+// prox_ac at every value of a stencil window (the values load_win reads: row dy
+// holds 4 + 2 (HY - |dy|) of them), all advanced by one Newton loop that stops
+// when every value has converged.  One loop rather than one per value keeps the
+// initial row pass within its register budget (no scratch spills).
+template <int HY>
+__device__ __forceinline__ void prox_ac_win(double (&v)[2 * HY + 1][4 + 2 * HY], double ht, double b) {
+    const double al = ht * b, be = 1.0 - ht * b;
+    double c[2 * HY + 1][4 + 2 * HY];
+#pragma unroll
+    for (int i = 0; i < 2 * HY + 1; ++i) {
+        const int hx = HY - (i < HY ? HY - i : i - HY);
+#pragma unroll
+        for (int j = HY - hx; j < HY + 4 + hx; ++j) c[i][j] = v[i][j];
+    }
+#pragma unroll 1
+    for (int n = 0; n < PROX_MAX_NEWTON; ++n) {
+        bool conv = true;
+#pragma unroll
+        for (int i = 0; i < 2 * HY + 1; ++i) {
+            const int hx = HY - (i < HY ? HY - i : i - HY);
+#pragma unroll
+            for (int j = HY - hx; j < HY + 4 + hx; ++j) {
+                const double u = v[i][j];
+                const double d = (al * u * u * u + be * u - c[i][j]) / (3.0 * al * u * u + be);
+                v[i][j] = u - d;
+                conv = conv && newton_converged(d, v[i][j]);
+            }
+        }
+        if (conv) break;
+    }
+}
 __device__ __forceinline__ void prox_schnak(double cu, double cv, double ht, double a, double b, double kap,
                                             double &u, double &v) {
     const double gam = ht * kap, B = cv + gam * b;
@@ -431,14 +462,14 @@ __device__ __forceinline__ void produce_W4(SlotRef s, StateRef sst, int y, int x
                 for (int k = 0; k < 4; ++k) uk[c][k] = wu[c].at(k, 0, 0);
             }
             if (s.init != 0) {
+                if constexpr (EQ == EQ_LAP5) {
+                    prox_ac_win<HY>(wu[0].v, s.ht, s.b);
+                } else if constexpr (EQ == EQ_SCHNAK) {
 #pragma unroll
-                for (int i = 0; i < 2 * HY + 1; ++i) {
-                    const int hx = HY - (i < HY ? HY - i : i - HY);
+                    for (int i = 0; i < 2 * HY + 1; ++i) {
+                        const int hx = HY - (i < HY ? HY - i : i - HY);
 #pragma unroll
-                    for (int j = HY - hx; j < HY + 4 + hx; ++j) {
-                        if constexpr (EQ == EQ_LAP5) {
-                            wu[0].v[i][j] = prox_ac(wu[0].v[i][j], s.ht, s.b);
-                        } else if constexpr (EQ == EQ_SCHNAK) {
+                        for (int j = HY - hx; j < HY + 4 + hx; ++j) {
                             double u, v;
                             prox_schnak(wu[0].v[i][j], wu[1].v[i][j], s.ht, s.sa, s.sb, s.kappa, u, v);
                             wu[0].v[i][j] = u;
@@ -998,9 +1029,10 @@ __device__ __forceinline__ void cols_regs(SlotRef s, int c, int kx0, cplx<T> *S,
     }
 }
 
-// FIN >= 0: the launch has one extra workgroup (the last) that takes the stop
-// decision of the preceding row pass of kind FIN, in parallel with the column
-// transforms.  The other workgroups test the State as it was before that
+// FIN >= 0: the launch has one extra workgroup (block 0, dispatched first, so that
+// it runs beside the column transforms also when the grid takes more than one
+// round of the CUs) that takes the stop decision of the preceding row pass of
+// kind FIN.  The other workgroups test the State as it was before that
 // decision: a slot that converges at this row pass runs one column pass more,
 // whose output nothing reads (the kernels after it see the decision).
 constexpr int FIN_NONE = -1;
@@ -1016,7 +1048,7 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>()), (col_waves_per_eu<T, L
     SlotRef s = slot_of(slots);
     StateRef sst = state_of(s);
     if constexpr (FIN != FIN_NONE) {
-        if (blockIdx.x == gridDim.x - 1) {
+        if (blockIdx.x == 0) {
             if (!skip_launch<FIN>(sst)) reduce_and_finalize<FIN, C, NTH>(s, lanes);
             return;
         }
@@ -1026,7 +1058,7 @@ __global__ __launch_bounds__((col_threads<T, LOGN, C>()), (col_waves_per_eu<T, L
     // inner loop (outer_done equals done in the FP64 path).
     if (sst.outer_done) return;
     // blockIdx.x -> (component, first column); CB divides N/2
-    const int bx = xcd_tile(blockIdx.x, C * (H / CB));
+    const int bx = xcd_tile((int)blockIdx.x - (FIN != FIN_NONE ? 1 : 0), C * (H / CB));
     const int c = bx / (H / CB);
     const int kx0 = (bx % (H / CB)) * CB;
     cplx<T> *S = (cplx<T> *)s.S;

@@ -694,7 +694,7 @@ __device__ __forceinline__ void lines_regs(SlotRef s, int c, int w, int j0, cplx
 
 // Lines of CB adjacent slots.  YFWD / YINV: the lines along y of plane (c, z);
 // ZSYM: the lines along z of row q (the y-transformed index) of component c.
-// FIN >= 0 (forward y pass only): one extra workgroup, the last, takes the stop
+// FIN >= 0 (forward y pass only): one extra workgroup, block 0, takes the stop
 // decision of the preceding row pass of kind FIN, as in the 2-D column pass.
 template <typename T, int LOGN, int BC, int C, int PASS, int FIN>
 __global__ __launch_bounds__((line_threads<T, LOGN>())) void k3_lines(Slot *const *slots) {
@@ -707,7 +707,7 @@ __global__ __launch_bounds__((line_threads<T, LOGN>())) void k3_lines(Slot *cons
     SlotRef s = slot_of(slots);
     StateRef sst = state_of(s);
     if constexpr (FIN != FIN_NONE) {
-        if (blockIdx.x == gridDim.x - 1) {
+        if (blockIdx.x == 0) {
             if (!skip_launch<FIN>(sst)) reduce_and_finalize<FIN, C, NTH>(s, lanes);
             return;
         }
@@ -720,7 +720,8 @@ __global__ __launch_bounds__((line_threads<T, LOGN>())) void k3_lines(Slot *cons
     // 256^3: consecutive blocks (adjacent slot groups, then lines) on one XCD
     // (FP64 line passes 20-25 % faster there; at 128^3 the round-robin order is
     // faster)
-    const int bxl = lines_xcd<LOGN>() ? xcd_tile(blockIdx.x, C * N * (H / CB)) : (int)blockIdx.x;
+    const int b0 = (int)blockIdx.x - (FIN != FIN_NONE ? 1 : 0);
+    const int bxl = lines_xcd<LOGN>() ? xcd_tile(b0, C * N * (H / CB)) : b0;
     const int grp = bxl % (H / CB), rest = bxl / (H / CB);
     const int w = rest % N, c = rest / N;
     const int j0 = grp * CB;

@@ -100,10 +100,27 @@ def test_step_neumann_512(ctx, rd, kind):
 
 
 @pytest.mark.parametrize("kind", ["allen_cahn", "schnakenberg"])
-def test_step_fp64_prox_init_matches_oracle(ctx, rd, kind):
-    cfg = small_cfg(kind, 64, "periodic")
+@pytest.mark.parametrize("N,bc", [(64, "periodic"), (256, "periodic"), (256, "neumann")])
+def test_step_fp64_prox_init_matches_oracle(ctx, rd, kind, N, bc):
+    """U_0 = prox(U^k): the single-workgroup step (64^2) and the batched initial pass (256^2)."""
+    cfg = small_cfg(kind, N, bc)
     tol = 1e-8 if kind == "allen_cahn" else 1e-7
-    compare_fp64(ctx, rd, cfg, wl.initial_field(cfg, N=64, seed=8), 2, tol=tol, init="prox")
+    compare_fp64(ctx, rd, cfg, wl.initial_field(cfg, N=N, seed=8), 2, tol=tol, init="prox")
+
+
+@pytest.mark.parametrize("kind", ["allen_cahn", "schnakenberg"])
+@pytest.mark.parametrize("N", [64, 256])
+def test_step_mixed_prox_init_matches_oracle(ctx, rd, kind, N):
+    """The mixed step from U_0 = prox(U^k) reaches the oracle's root within the mixed bar."""
+    cfg = small_cfg(kind, N, "periodic")
+    tol = 1e-8 if kind == "allen_cahn" else 1e-7
+    op = oracle_problem(cfg)
+    U = wl.initial_field(cfg, N=N, seed=8)
+    r = opdhg.step(op, U, cfg["ht"], oracle_opts(cfg, tol=tol, init="prox"))
+    Ug, info = ctx.step(dev(U), cfg["ht"], rd.problem_from_config(cfg),
+                        gpu_opts(rd, cfg, precision="mixed", tol=tol, init="prox"))
+    assert info["status"] == "ok" and info["residual"] <= tol, info
+    assert max_abs(Ug.cpu().numpy(), r.U) <= 1e-5
 
 
 @pytest.mark.parametrize("kind", ["allen_cahn", "cahn_hilliard", "schnakenberg"])

@@ -234,8 +234,20 @@ def config_leg(ctx, rd, torch, wl, name, precs, steps=None, oracle=True):
     u0 = torch.tensor(u0_np, dtype=torch.float64, device="cuda")
     out = dict(workload=name, N=cfg["N"], steps=n)
     firsts = {}
+    ncomp = 2 if cfg["kind"] == "schnakenberg" else 1
     for prec in precs:
         out[prec], firsts[prec], _ = run_precision(ctx, rd, torch, cfg, u0, prec, n, 2)
+        if cfg["N"] > 64:
+            # the iteration's launches (HIP events) against the survey's bytes per
+            # grid-point-iteration, times the number of species
+            p = rd.problem_from_config(cfg)
+            o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], omega=cfg["omega"], precision=prec)
+            ms = ctx.profile_iteration(u0, cfg["ht"], p, o, reps=20)
+            it_ms = sum(ms.values())
+            b = ALG_BYTES[prec] * ncomp * cfg["N"] ** 2
+            out[prec]["iteration"] = dict(kernels_us={k: round(v * 1e3, 2) for k, v in ms.items()},
+                                          us=round(it_ms * 1e3, 2), bytes=b,
+                                          frac=round(b / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
     if oracle:
         ref, timing = oracle_step(cfg, u0_np)
         out["oracle_step1"] = dict(timing, residual=ref.residual, status=ref.status)

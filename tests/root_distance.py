@@ -9,15 +9,18 @@ FP64 round-off floor of the plain norm (Sec. 2.1 stopping criterion; the step's 
 is unique for these parameters, so both references are the same point up to that
 floor).
 
-    python -m oracle.root_distance ac64 ch512 schnak1024:1e-7 ac2048:1e-8
+    python tests/root_distance.py ac64 ch512 schnak1024:1e-7 ac2048:1e-8
 
 Each argument is a workload name, optionally followed by ":tol" to use the tight
 Algorithm-1 reference at that tolerance instead of Newton.  Prints one JSON line per
 workload.
 """
 import json
+import os
 import sys
 import time
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 import numpy as np
 

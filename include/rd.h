@@ -127,7 +127,7 @@ rd_status rd_create(int device, void **out);
 rd_status rd_destroy(void *ctx);
 
 /* Default options: tol 1e-10, max_iter 10000, max_outer 20, tau_u = tau_p = 0.9,
- * omega = 1, FP64, U_0 = U^k, inner_rtol 1e-3.                                             */
+ * omega = 1, FP64, U_0 = U^k, inner_rtol 3e-2.                                             */
 void rd_default_opts(rd_opts *opts);
 
 /* Device bytes one step's workspace needs (fields, spectra, partial sums).              */

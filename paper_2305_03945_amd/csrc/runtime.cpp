@@ -622,7 +622,7 @@ void rd_default_opts(rd_opts *o) {
     o->omega = 1.0;
     o->precision = RD_FP64;
     o->init = RD_INIT_PREV;
-    o->inner_rtol = 1e-3;
+    o->inner_rtol = 3e-2;
 }
 
 rd_status rd_create(int device, void **out) {

@@ -177,7 +177,7 @@ def problem_from_config(cfg, N=None, bc=None):
 
 
 def make_opts(tol=1e-10, max_iter=10000, tau_u=0.9, tau_p=0.9, omega=1.0, precision="fp64", init="prev",
-              inner_rtol=1e-3, max_outer=20):
+              inner_rtol=3e-2, max_outer=20):
     o = Opts()
     _lib.rd_default_opts(ctypes.byref(o))
     o.tol = float(tol)

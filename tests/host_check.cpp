@@ -281,6 +281,7 @@ rd_opts opts(double tol, int prec) {
     rd_default_opts(&o);
     o.tol = tol;
     o.precision = prec;
+    o.inner_rtol = 1e-3;   // the inner-loop lengths the scenarios expect
     return o;
 }
 

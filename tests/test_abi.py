@@ -69,7 +69,7 @@ def test_default_opts_and_status_strings(rd):
     o = rd.Opts()
     rd._lib.rd_default_opts(ctypes.byref(o))
     assert (o.tol, o.max_iter, o.max_outer, o.tau_u, o.tau_p, o.omega) == (1e-10, 10000, 20, 0.9, 0.9, 1.0)
-    assert (o.precision, o.init, o.inner_rtol) == (rd.RD_FP64, rd.RD_INIT_PREV, 1e-3)
+    assert (o.precision, o.init, o.inner_rtol) == (rd.RD_FP64, rd.RD_INIT_PREV, 3e-2)
     for code in (rd.RD_OK, rd.RD_E_INVALID, rd.RD_E_NOCONV, rd.RD_E_NONFINITE, rd.RD_E_NOMEM, rd.RD_E_DEVICE,
                  rd.RD_E_BUSY):
         s = rd.status_str(code)

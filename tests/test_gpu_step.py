@@ -30,7 +30,7 @@ def dev(x):
     return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
 
 
-def gpu_opts(rd, cfg, precision="fp64", tol=None, max_iter=10000, init="prev", inner_rtol=1e-3):
+def gpu_opts(rd, cfg, precision="fp64", tol=None, max_iter=10000, init="prev", inner_rtol=3e-2):
     return rd.make_opts(tol=cfg["tol"] if tol is None else tol, max_iter=max_iter, tau_u=cfg["tau"],
                         tau_p=cfg["tau"], omega=cfg["omega"], precision=precision, init=init,
                         inner_rtol=inner_rtol)

@@ -121,10 +121,16 @@ typedef struct {
 } rd_info;
 
 /* ---- context ---------------------------------------------------------------------- */
+/* Opaque handles: a context (one device, its workspaces, tables and serving state) and a
+ * serving trajectory of that context.  Owned by the library; freed by rd_destroy and
+ * rd_traj_close.                                                                          */
+typedef struct rd_ctx rd_ctx;
+typedef struct rd_traj rd_traj;
+
 /* Create a context on HIP device `device`.  *out receives the handle.                    */
-rd_status rd_create(int device, void **out);
+rd_status rd_create(int device, rd_ctx **out);
 /* Free every workspace and table of the context.                                         */
-rd_status rd_destroy(void *ctx);
+rd_status rd_destroy(rd_ctx *ctx);
 
 /* Default options: tol 1e-10, max_iter 10000, max_outer 20, tau_u = tau_p = 0.9,
  * omega = 1, FP64, U_0 = U^k, inner_rtol 3e-2.                                             */
@@ -138,7 +144,7 @@ size_t rd_footprint_bytes(const rd_problem *prob, const rd_opts *opts);
  * hipStream_t or NULL.  info (HOST) receives iteration count, residuals, mass drift and
  * status; the return value equals info->status, or an argument/device error code.
  * Synchronises the stream.                                                               */
-rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
+rd_status rd_step(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
                   const double *u_n, double *u_np1, void *hip_stream, rd_info *info);
 
 /* ---- one implicit step without allocation ------------------------------------------ */
@@ -155,7 +161,7 @@ rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double
  * rewrites what it reads first), so calls that overlap on one device -- from several
  * threads or contexts, or on several streams -- race and must not be made.
  * Synchronises the stream.                                                               */
-rd_status rd_step_noalloc(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
+rd_status rd_step_noalloc(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
                           const double *u_n, double *u_np1, void *hip_stream, rd_info *info);
 
 /* ---- adaptive time step size (Sec. 2.2, "Adaptive time stepsize") ---------------------- */
@@ -200,25 +206,25 @@ rd_status rd_adapt_next(const rd_adapt *adapt, double h, int32_t iters, int32_t 
  * each) receive the size, iteration count and acceptance of the first trace_cap solves.
  * Allocates one field-sized device buffer for the call.  Returns info->status, or an
  * argument / device error.  Synchronises.                                                */
-rd_status rd_advance(void *ctx, const rd_problem *prob, const rd_opts *opts, const rd_adapt *adapt,
+rd_status rd_advance(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts, const rd_adapt *adapt,
                      double t0, double t_end, double *u, void *hip_stream, rd_adapt_info *info,
                      double *trace_h, int32_t *trace_iters, int32_t *trace_ok, int32_t trace_cap);
 
 /* ---- kernel-level entry points (the pieces of one iteration) ------------------------ */
 /* W = F(U) (Sec. 2.1 eq. 12; Sec. 3.2 eq. 29; Sec. 3.4.1).  u, uk, w: DEVICE, [c][N][N].
  * *res_l2 (HOST) receives ||W / h_t||_2 summed over components.  Synchronises.          */
-rd_status rd_residual(void *ctx, const rd_problem *prob, double h_t, const double *u,
+rd_status rd_residual(rd_ctx *ctx, const rd_problem *prob, double h_t, const double *u,
                       const double *uk, double *w, void *hip_stream, double *res_l2);
 /* Y = G^-1 W with G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2 per component as the
  * equation implies (Sec. 2.1 "Choosing the matrix G"; Remark 1 for Neumann; Sec. 3.3 for
  * gamma).  w, y: DEVICE, [c][N][N] or [c][N][N][N].  precision RD_FP64 or RD_FP32_MIXED
  * (FP32 transforms; FP64 only for RD_OP_FCH6).  Synchronises.                               */
-rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_t precision,
+rd_status rd_precond_solve(rd_ctx *ctx, const rd_problem *prob, double h_t, int32_t precision,
                            const double *w, double *y, void *hip_stream);
 /* Pointwise reaction prox (the implicit reaction-only step, a predictor for U_0;
  * Sec. 2.1 "Initial guess"): Allen-Cahn cubic, Schnakenberg 2x2; identity otherwise.
  * c, u: DEVICE.  Synchronises.                                                            */
-rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *c, double *u,
+rd_status rd_prox(rd_ctx *ctx, const rd_problem *prob, double h_t, const double *c, double *u,
                   void *hip_stream);
 
 /* ---- instrumentation ------------------------------------------------------------- */
@@ -233,7 +239,7 @@ rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *c
  * 3-D: forward y-line pass (with the stop decision of the preceding row pass), z-line
  * pass (forward, symbol, inverse), inverse y-line pass, inverse x-row pass + dual
  * update, primal update, residual + forward x-row pass.  Synchronises.                 */
-rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
+rd_status rd_profile_iteration(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
                                const double *u_n, int32_t reps, void *hip_stream, double *ms_out);
 
 /* ---- serving: continuous batching of steps of resident trajectories ----------------- */
@@ -251,26 +257,28 @@ rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts 
 /* Set the device-memory budget for admitted trajectories (bytes; 0 = unlimited).  A
  * trajectory is admitted while resident + its workspace <= budget, and always when
  * nothing is resident (so a single request larger than the budget still runs).        */
-rd_status rd_serve_set_budget(void *ctx, size_t bytes);
+rd_status rd_serve_set_budget(rd_ctx *ctx, size_t bytes);
 /* Open a trajectory: copies u0 (DEVICE, FP64, [c][N][N] or [c][N][N][N]) into a resident copy, ordered
  * after prior work on hip_stream, and synchronises it.  *out (HOST) receives the handle.
  * Workspace memory is reserved only at admission, by rd_serve_pump.                    */
-rd_status rd_traj_open(void *ctx, const rd_problem *prob, const rd_opts *opts,
-                       const double *u0, void *hip_stream, void **out);
+rd_status rd_traj_open(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts,
+                       const double *u0, void *hip_stream, rd_traj **out);
 /* Queue one implicit step of size h_t; *ticket (HOST) identifies it.  Steps of one
  * trajectory run in submission order, each starting from the previous one's result.    */
-rd_status rd_traj_submit(void *traj, double h_t, uint64_t *ticket);
-/* One serving round (admit, start, advance, retire).  max_wait_us is reserved and must
- * be >= 0; the call returns after one round.                                              */
-rd_status rd_serve_pump(void *ctx, int32_t max_wait_us);
+rd_status rd_traj_submit(rd_traj *traj, double h_t, uint64_t *ticket);
+/* One serving round: admits queued trajectories, retires the rounds that have completed,
+ * starts a round for every idle group with work; if no round had completed, waits for the
+ * first in-flight one to complete (at most max_wait_us microseconds when > 0, no limit when
+ * 0), retires it and restarts its group.  max_wait_us < 0: RD_E_INVALID.                   */
+rd_status rd_serve_pump(rd_ctx *ctx, int32_t max_wait_us);
 /* RD_E_BUSY until the ticket's step finished; then fills info (HOST) and returns the
  * step's status.  RD_E_INVALID for an unknown ticket.                                   */
-rd_status rd_poll(void *ctx, uint64_t ticket, rd_info *info);
+rd_status rd_poll(rd_ctx *ctx, uint64_t ticket, rd_info *info);
 /* Copy the trajectory's current state U^k to u_out (DEVICE).  Synchronises.            */
-rd_status rd_traj_read(void *traj, double *u_out, void *hip_stream);
+rd_status rd_traj_read(rd_traj *traj, double *u_out, void *hip_stream);
 /* Close a trajectory: waits for the device, releases its workspace (returning its bytes
  * to the budget) and its resident state.  Unfinished tickets of it stay RD_E_BUSY.      */
-rd_status rd_traj_close(void *traj);
+rd_status rd_traj_close(rd_traj *traj);
 
 typedef struct {
     uint64_t budget_bytes;   /* as set by rd_serve_set_budget                              */
@@ -281,7 +289,7 @@ typedef struct {
     int32_t pending_steps;   /* submitted steps not started yet                            */
 } rd_serve_info;
 /* Snapshot of the serving state (HOST out).  Host-only; no device work.                */
-rd_status rd_serve_stats(void *ctx, rd_serve_info *out);
+rd_status rd_serve_stats(rd_ctx *ctx, rd_serve_info *out);
 
 const char *rd_status_str(rd_status s);
 

@@ -625,7 +625,7 @@ void rd_default_opts(rd_opts *o) {
     o->inner_rtol = 3e-2;
 }
 
-rd_status rd_create(int device, void **out) {
+rd_status rd_create(int device, rd_ctx **out) {
     if (!out) return RD_E_INVALID;
     *out = nullptr;
     int n = 0;
@@ -643,11 +643,11 @@ rd_status rd_create(int device, void **out) {
         delete c;
         return RD_E_NOMEM;
     }
-    *out = c;
+    *out = (rd_ctx *)c;
     return RD_OK;
 }
 
-rd_status rd_destroy(void *ctx) {
+rd_status rd_destroy(rd_ctx *ctx) {
     if (!ctx) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
     (void)hipSetDevice(c->device);
@@ -691,7 +691,7 @@ size_t rd_footprint_bytes(const rd_problem *prob, const rd_opts *opts) {
     return workspace_bytes(d.pts, d.rows, d.C, mode, rpb) + field_bytes(d.pts, d.C, 8);
 }
 
-rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t, const double *u_n,
+rd_status rd_step(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts, double h_t, const double *u_n,
                   double *u_np1, void *hip_stream, rd_info *info) {
     if (!ctx || !u_n || !u_np1) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
@@ -742,7 +742,7 @@ rd_status rd_step(void *ctx, const rd_problem *prob, const rd_opts *opts, double
     return (rd_status)sf.status;
 }
 
-rd_status rd_step_noalloc(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t, const double *u_n,
+rd_status rd_step_noalloc(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts, double h_t, const double *u_n,
                           double *u_np1, void *hip_stream, rd_info *info) {
     if (!ctx || !u_n || !u_np1) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
@@ -857,7 +857,7 @@ rd_status rd_step_noalloc(void *ctx, const rd_problem *prob, const rd_opts *opts
     return (rd_status)sf.status;
 }
 
-rd_status rd_profile_iteration(void *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
+rd_status rd_profile_iteration(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts, double h_t,
                                const double *u_n, int32_t reps, void *hip_stream, double *ms_out) {
     if (!ctx || !u_n || !ms_out || reps <= 0) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
@@ -966,7 +966,7 @@ rd_status rd_adapt_next(const rd_adapt *a, double h, int32_t iters, int32_t step
     return RD_OK;
 }
 
-rd_status rd_advance(void *ctx, const rd_problem *prob, const rd_opts *opts, const rd_adapt *a, double t0,
+rd_status rd_advance(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts, const rd_adapt *a, double t0,
                      double t_end, double *u, void *hip_stream, rd_adapt_info *info, double *trace_h,
                      int32_t *trace_iters, int32_t *trace_ok, int32_t trace_cap) {
     if (!ctx || !u || !info || !check_adapt(a) || !std::isfinite(t0) || !std::isfinite(t_end) || t_end < t0)
@@ -1034,7 +1034,7 @@ rd_status rd_advance(void *ctx, const rd_problem *prob, const rd_opts *opts, con
 }
 
 // ---------------------------------------------------------------- kernel-level entry points
-rd_status rd_residual(void *ctx, const rd_problem *prob, double h_t, const double *u, const double *uk, double *w,
+rd_status rd_residual(rd_ctx *ctx, const rd_problem *prob, double h_t, const double *u, const double *uk, double *w,
                       void *hip_stream, double *res_l2) {
     if (!ctx || !u || !uk || !w) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
@@ -1075,7 +1075,7 @@ rd_status rd_residual(void *ctx, const rd_problem *prob, double h_t, const doubl
     return RD_OK;
 }
 
-rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_t precision, const double *w_in,
+rd_status rd_precond_solve(rd_ctx *ctx, const rd_problem *prob, double h_t, int32_t precision, const double *w_in,
                            double *y, void *hip_stream) {
     if (!ctx || !w_in || !y) return RD_E_INVALID;
     if (precision != RD_FP64 && precision != RD_FP32_MIXED) return RD_E_INVALID;
@@ -1113,7 +1113,7 @@ rd_status rd_precond_solve(void *ctx, const rd_problem *prob, double h_t, int32_
     return RD_OK;
 }
 
-rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *cin, double *u, void *hip_stream) {
+rd_status rd_prox(rd_ctx *ctx, const rd_problem *prob, double h_t, const double *cin, double *u, void *hip_stream) {
     if (!ctx || !cin || !u) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
     Desc d;
@@ -1133,14 +1133,14 @@ rd_status rd_prox(void *ctx, const rd_problem *prob, double h_t, const double *c
 }
 
 // ---------------------------------------------------------------- serving
-rd_status rd_serve_set_budget(void *ctx, size_t bytes) {
+rd_status rd_serve_set_budget(rd_ctx *ctx, size_t bytes) {
     if (!ctx) return RD_E_INVALID;
     ((Ctx *)ctx)->budget = bytes;
     return RD_OK;
 }
 
-rd_status rd_traj_open(void *ctx, const rd_problem *prob, const rd_opts *opts, const double *u0, void *hip_stream,
-                       void **out) {
+rd_status rd_traj_open(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts, const double *u0, void *hip_stream,
+                       rd_traj **out) {
     if (!ctx || !u0 || !out) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
     Desc d;
@@ -1171,11 +1171,11 @@ rd_status rd_traj_open(void *ctx, const rd_problem *prob, const rd_opts *opts, c
         return RD_E_DEVICE;
     }
     c->trajs.push_back(t);
-    *out = t;
+    *out = (rd_traj *)t;
     return RD_OK;
 }
 
-rd_status rd_traj_submit(void *traj, double h_t, uint64_t *ticket) {
+rd_status rd_traj_submit(rd_traj *traj, double h_t, uint64_t *ticket) {
     if (!traj || !ticket || !(h_t > 0.0) || !std::isfinite(h_t)) return RD_E_INVALID;
     Traj *t = (Traj *)traj;
     Ctx *c = t->ctx;
@@ -1347,7 +1347,7 @@ rd_status launch_rounds(Ctx *c) {
 
 extern "C" {
 
-rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
+rd_status rd_serve_pump(rd_ctx *ctx, int32_t max_wait_us) {
     if (!ctx || max_wait_us < 0) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
     RD_CHECK(hipSetDevice(c->device));
@@ -1391,7 +1391,7 @@ rd_status rd_serve_pump(void *ctx, int32_t max_wait_us) {
     return RD_OK;
 }
 
-rd_status rd_serve_stats(void *ctx, rd_serve_info *out) {
+rd_status rd_serve_stats(rd_ctx *ctx, rd_serve_info *out) {
     if (!ctx || !out) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
     std::memset(out, 0, sizeof(*out));
@@ -1406,7 +1406,7 @@ rd_status rd_serve_stats(void *ctx, rd_serve_info *out) {
     return RD_OK;
 }
 
-rd_status rd_poll(void *ctx, uint64_t ticket, rd_info *info) {
+rd_status rd_poll(rd_ctx *ctx, uint64_t ticket, rd_info *info) {
     if (!ctx) return RD_E_INVALID;
     Ctx *c = (Ctx *)ctx;
     auto it = c->tickets.find(ticket);
@@ -1416,7 +1416,7 @@ rd_status rd_poll(void *ctx, uint64_t ticket, rd_info *info) {
     return (rd_status)it->second.info.status;
 }
 
-rd_status rd_traj_read(void *traj, double *u_out, void *hip_stream) {
+rd_status rd_traj_read(rd_traj *traj, double *u_out, void *hip_stream) {
     if (!traj || !u_out) return RD_E_INVALID;
     Traj *t = (Traj *)traj;
     RD_CHECK(hipSetDevice(t->ctx->device));
@@ -1426,7 +1426,7 @@ rd_status rd_traj_read(void *traj, double *u_out, void *hip_stream) {
     return RD_OK;
 }
 
-rd_status rd_traj_close(void *traj) {
+rd_status rd_traj_close(rd_traj *traj) {
     if (!traj) return RD_E_INVALID;
     Traj *t = (Traj *)traj;
     Ctx *c = t->ctx;

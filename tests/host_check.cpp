@@ -309,7 +309,7 @@ bool all_equal(const double *a, size_t n, double v) {
 }
 
 void validation() {
-    void *ctx = nullptr, *other = nullptr;
+    rd_ctx *ctx = nullptr, *other = nullptr;
     CHECK(rd_create(1, &other) == RD_E_INVALID && other == nullptr);
     CHECK(rd_create(0, &ctx) == RD_OK);
     CHECK(rd_create(0, nullptr) == RD_E_INVALID);
@@ -351,7 +351,7 @@ void validation() {
 }
 
 void fp64_steps() {
-    void *ctx = nullptr;
+    rd_ctx *ctx = nullptr;
     rd_create(0, &ctx);
     const int N = 32;
     const size_t n = (size_t)N * N;
@@ -406,7 +406,7 @@ void fp64_steps() {
 }
 
 void mixed_steps() {
-    void *ctx = nullptr;
+    rd_ctx *ctx = nullptr;
     rd_create(0, &ctx);
     const int N = 16;
     const size_t n = 2 * (size_t)N * N;
@@ -441,12 +441,12 @@ void mixed_steps() {
 }
 
 void serving() {
-    void *ctx = nullptr;
+    rd_ctx *ctx = nullptr;
     rd_create(0, &ctx);
     struct T {
         int N, prec, steps;
         double ht, tol;
-        void *h;
+        rd_traj *h;
         double *u;
         std::vector<uint64_t> tickets;
     };
@@ -531,7 +531,7 @@ void adaptive() {
     bad.eta = 1.0;
     CHECK(rd_adapt_next(&bad, 0.01, 8, RD_OK, &nx, &acc) == RD_E_INVALID);
     // a run: q(h) makes large steps take many iterations, so the rule settles
-    void *ctx = nullptr;
+    rd_ctx *ctx = nullptr;
     rd_create(0, &ctx);
     const int N = 16;
     rd_problem p = ac(N);
@@ -591,7 +591,7 @@ void column_pass_race_invariant() {
 // allocation (the stub's live-allocation count does not move during the calls);
 // problems beyond the array are refused.
 void noalloc_steps() {
-    void *ctx = nullptr;
+    rd_ctx *ctx = nullptr;
     rd_create(0, &ctx);
     for (int prec : {RD_FP64, RD_FP32_MIXED}) {
         for (int N : {256, 32}) {
@@ -630,14 +630,14 @@ void noalloc_steps() {
 void teardown_returns_everything() {
     const long base = hipstub::live_allocs();
     for (int r = 0; r < 20; ++r) {
-        void *ctx = nullptr;
+        rd_ctx *ctx = nullptr;
         rd_create(0, &ctx);
         rd_problem p = ac(16);
         rd_opts o = opts(1e-3, r & 1 ? RD_FP32_MIXED : RD_FP64);
         double *u = dalloc(256);
         rd_info info;
         rd_step(ctx, &p, &o, 0.01, u, u, nullptr, &info);
-        void *t = nullptr;
+        rd_traj *t = nullptr;
         rd_traj_open(ctx, &p, &o, u, nullptr, &t);
         uint64_t tk;
         rd_traj_submit(t, 0.01, &tk);

@@ -152,11 +152,13 @@ def oracle_step(cfg, u0_np):
     """The FP64 oracle (Algorithm 1, numpy, as it stands) on one step: result and timing."""
     from oracle import pdhg as opdhg
     from tests.rd_cases import oracle_opts, oracle_problem
-    t0, c0 = time.perf_counter(), os.times()
+    # cores: CPU time of this thread over wall time (the oracle's numpy FFTs and scipy
+    # sparse products run on the calling thread; process-wide CPU time would also count
+    # the GPU runtime's own threads)
+    t0, c0 = time.perf_counter(), time.thread_time()
     r = opdhg.step(oracle_problem(cfg), u0_np, cfg["ht"], oracle_opts(cfg))
     wall = time.perf_counter() - t0
-    c1 = os.times()
-    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    cpu = time.thread_time() - c0
     pts = cfg["N"] ** cfg.get("dim", 2)
     return r, dict(pt_iters_per_s=pts * r.iters / wall, step_ms=1e3 * wall, iters=r.iters,
                    cores=max(1, round(cpu / wall)))

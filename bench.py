@@ -240,8 +240,8 @@ def config_leg(ctx, rd, torch, wl, name, precs, steps=None, oracle=True):
     for prec in precs:
         out[prec], firsts[prec], _ = run_precision(ctx, rd, torch, cfg, u0, prec, n, 2)
         if cfg["N"] > 64:
-            # the iteration's launches (HIP events) against the survey's bytes per
-            # grid-point-iteration, times the number of species
+            # the iteration's launches (HIP events) against ALG_BYTES, the bytes one
+            # iteration must move per grid point, times the number of species
             p = rd.problem_from_config(cfg)
             o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], omega=cfg["omega"], precision=prec)
             ms = ctx.profile_iteration(u0, cfg["ht"], p, o, reps=20)

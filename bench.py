@@ -432,7 +432,7 @@ def paper_examples_leg(ctx, rd, torch, wl, steps):
                                    iters_last=iters[-1], ms_per_step=1e3 * wall / n,
                                    p50_ms=1e3 * percentile(lat, 50), pt_iters_per_s=pts * sum(iters) / wall)
     out["paper_counts"] = {"schnakenberg_sec3.4.1": "about 30 iterations per step",
-                           "allen_cahn_circle_sec3.1.1": "fewer than 200 iterations per step"}
+                           "allen_cahn_circle_sec3.1.1": "mostly below 200 iterations per step"}
     return out
 
 

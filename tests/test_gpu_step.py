@@ -65,7 +65,7 @@ def test_ac64_ten_steps_fp64(ctx, rd):
 
 @pytest.mark.parametrize("kind", ["allen_cahn", "cahn_hilliard", "schnakenberg"])
 @pytest.mark.parametrize("bc", ["periodic", "neumann"])
-@pytest.mark.parametrize("N", [16, 128])
+@pytest.mark.parametrize("N", [16, 64, 128])
 def test_step_fp64_matches_oracle(ctx, rd, kind, bc, N):
     cfg = small_cfg(kind, N, bc)
     tol = {"allen_cahn": 1e-8, "cahn_hilliard": 1e-5, "schnakenberg": 1e-7}[kind]
@@ -86,13 +86,13 @@ def test_step_periodic_large_columns(ctx, rd, kind, N):
     assert max_abs(Ug.cpu().numpy(), U1) <= 1e-5
 
 
-@pytest.mark.parametrize("kind", ["allen_cahn", "schnakenberg"])
-def test_step_neumann_512(ctx, rd, kind):
-    """Neumann (DCT-II) grid of 512^2, two rows per row workgroup: one step in FP64
-    (equal iterations, 1e-10) and in mixed precision (1e-5)."""
-    cfg = small_cfg(kind, 512, "neumann")
+@pytest.mark.parametrize("kind,N", [("allen_cahn", 512), ("schnakenberg", 512), ("allen_cahn", 1024)])
+def test_step_neumann_large(ctx, rd, kind, N):
+    """Neumann (DCT-II) grids of 512^2 (two rows per row workgroup) and 1024^2 (four):
+    one step in FP64 (equal iterations, 1e-10) and in mixed precision (1e-5)."""
+    cfg = small_cfg(kind, N, "neumann")
     tol = 1e-7 if kind == "allen_cahn" else 1e-5
-    U0 = wl.initial_field(cfg, N=512, seed=17)
+    U0 = wl.initial_field(cfg, N=N, seed=17)
     U1 = compare_fp64(ctx, rd, cfg, U0, 1, tol=tol)
     Ug, info = ctx.step(dev(U0), cfg["ht"], rd.problem_from_config(cfg), gpu_opts(rd, cfg, "mixed", tol=tol))
     assert info["status"] == "ok" and info["residual"] <= tol
@@ -125,7 +125,7 @@ def test_step_mixed_prox_init_matches_oracle(ctx, rd, kind, N):
 
 @pytest.mark.parametrize("kind", ["allen_cahn", "cahn_hilliard", "schnakenberg"])
 @pytest.mark.parametrize("bc", ["periodic", "neumann"])
-@pytest.mark.parametrize("N", [32, 256])
+@pytest.mark.parametrize("N", [32, 64, 256])
 def test_step_mixed_matches_oracle(ctx, rd, kind, bc, N):
     cfg = small_cfg(kind, N, bc)
     tol = {"allen_cahn": 1e-8, "cahn_hilliard": 1e-5, "schnakenberg": 1e-7}[kind]

@@ -1,5 +1,5 @@
 """GPU parity at the workload sizes (2048^2 Allen-Cahn, 512^2 Cahn-Hilliard, 1024^2 Schnakenberg)
-and at the largest supported grid (4096^2), through the C ABI."""
+and at the largest supported grids (4096^2, 256^3), through the C ABI."""
 import numpy as np
 import pytest
 
@@ -107,6 +107,41 @@ def test_ac2048_three_steps_elementwise(ctx, rd, ac2048_oracle_steps, precision,
     p = rd.problem_from_config(cfg)
     u = dev(wl.initial_field(cfg))
     for k, ref in enumerate(ac2048_oracle_steps):
+        u, info = ctx.step(u, cfg["ht"], p, o)
+        assert info["status"] == "ok", (k, info)
+        if precision == "fp64":
+            assert info["iters"] == ref.iters, (k, info["iters"], ref.iters)
+        assert max_abs(u.cpu().numpy(), ref.U) <= bar, k
+
+
+_TRAJ = {}
+
+
+def _oracle_trajectory(name, n):
+    """The oracle's first n steps of a workload's trajectory (cached per module)."""
+    if name not in _TRAJ:
+        cfg = wl.CONFIGS[name]
+        U = wl.initial_field(cfg)
+        out = []
+        for _ in range(n):
+            r = opdhg.step(oracle_problem(cfg), U, cfg["ht"], oracle_opts(cfg))
+            out.append(r)
+            U = r.U
+        _TRAJ[name] = out
+    return _TRAJ[name]
+
+
+@pytest.mark.parametrize("name", ["ch512", "schnak1024"])
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_workload_three_steps_elementwise(ctx, rd, name, precision, bar):
+    """Steps 1-3 of the 512^2 Neumann Cahn-Hilliard and 1024^2 Schnakenberg trajectories,
+    every grid point against the oracle's, each GPU step starting from the GPU's previous
+    result (FP64: equal iteration counts)."""
+    cfg = wl.CONFIGS[name]
+    o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], omega=cfg["omega"], precision=precision)
+    p = rd.problem_from_config(cfg)
+    u = dev(wl.initial_field(cfg))
+    for k, ref in enumerate(_oracle_trajectory(name, 3)):
         u, info = ctx.step(u, cfg["ht"], p, o)
         assert info["status"] == "ok", (k, info)
         if precision == "fp64":

@@ -64,7 +64,7 @@ def test_precond_3d(ctx, rd, kind, bc, N):
 
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("bc", BCS)
-@pytest.mark.parametrize("N", [16, 32])
+@pytest.mark.parametrize("N", [16, 32, 64])
 def test_step_3d_fp64_and_mixed(ctx, rd, kind, bc, N):
     cfg = cfg3(kind, N, bc)
     op = oracle_problem(cfg)

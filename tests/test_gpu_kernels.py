@@ -41,7 +41,7 @@ def field(prob, seed, base=None):
 
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("bc", BCS)
-@pytest.mark.parametrize("N", [16, 64, 256])
+@pytest.mark.parametrize("N", [16, 64, 256, 2048])
 def test_residual_matches_oracle(ctx, rd, kind, bc, N):
     cfg = small_cfg(kind, N, bc)
     op = oracle_problem(cfg)
@@ -97,8 +97,9 @@ def test_precond_solve_fp32_matches_oracle(ctx, rd, kind, bc, N):
 
 
 @pytest.mark.parametrize("kind", ["allen_cahn", "schnakenberg"])
-def test_prox_matches_oracle(ctx, rd, kind):
-    cfg = small_cfg(kind, 64, "periodic")
+@pytest.mark.parametrize("N", [64, 256])
+def test_prox_matches_oracle(ctx, rd, kind, N):
+    cfg = small_cfg(kind, N, "periodic")
     op = oracle_problem(cfg)
     ht = 5e-2
     c = field(op, 3)

@@ -36,6 +36,19 @@ HBM_PEAK_GBS = 8000.0
 # the inverse row pass reads it).  A mixed outer FP64 pass moves 44 B per point.
 ALG_BYTES = {"fp64": 72, "mixed": 40}
 OUTER_BYTES = 44
+# The same count on an N^3 grid: the x transforms stay in the row passes and each of
+# the three line passes (forward y, z with the symbol, inverse y) reads and writes the
+# spectrum once, two round trips more than the single 2-D column pass.
+ALG_BYTES_3D = {"fp64": 104, "mixed": 56}
+
+
+def iteration_hbm(kernels, alg_bytes_per_point, pts):
+    """Whole-iteration HBM figure from a kernel table: the algorithmic bytes of one
+    iteration over the summed kernel durations, and its fraction of the HBM peak."""
+    it_ms = sum(v["ms"] for v in kernels.values())
+    b = alg_bytes_per_point * pts
+    return dict(us=round(it_ms * 1e3, 2), bytes=b, achieved=round(b / (it_ms * 1e-3) / 1e9, 1),
+                frac=round(b / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
 
 # Algorithmic HBM bytes per grid point and launch of each kernel (one component):
 # every field the kernel must read or write once, nothing for tables or halos.
@@ -385,6 +398,7 @@ def hbm_leg(ctx, rd, torch, wl, steps):
         it_bytes = sum(v["bytes"] for v in k.values())
         out[prec]["kernels"] = k
         out[prec]["iteration_gbs"] = it_bytes / (it_ms * 1e-3) / 1e9
+        out[prec]["iteration"] = iteration_hbm(k, ALG_BYTES[prec], pts)
     del u0
     torch.cuda.empty_cache()
     return out
@@ -449,6 +463,8 @@ def grid3d_leg(ctx, rd, torch, wl, steps):
     out["mixed_vs_fp64_final_maxabs"] = float((finals["mixed"] - finals["fp64"]).abs().max().item())
     out["speedup_mixed_vs_fp64"] = out["fp64"]["wall_s"] / out["mixed"]["wall_s"]
     out["kernels"] = {prec: kernel_table(ctx, rd, cfg, u0, prec, cfg["N"] ** 3) for prec in ("fp64", "mixed")}
+    for prec in ("fp64", "mixed"):
+        out[prec]["iteration"] = iteration_hbm(out["kernels"][prec], ALG_BYTES_3D[prec], cfg["N"] ** 3)
     # the largest 3-D grid, the same parameters: rate and kernels at 16.8 M points
     big = dict(cfg, N=256)
     u1 = torch.tensor(wl.initial_field(big), dtype=torch.float64, device="cuda")
@@ -456,6 +472,7 @@ def grid3d_leg(ctx, rd, torch, wl, steps):
     for prec in ("fp64", "mixed"):
         out["n256"][prec], _, _ = run_precision(ctx, rd, torch, big, u1, prec, min(n, 10), 1)
         out["n256"][prec]["kernels"] = kernel_table(ctx, rd, big, u1, prec, 256 ** 3)
+        out["n256"][prec]["iteration"] = iteration_hbm(out["n256"][prec]["kernels"], ALG_BYTES_3D[prec], 256 ** 3)
     del u1
     torch.cuda.empty_cache()
     return out

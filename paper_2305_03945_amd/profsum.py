@@ -11,6 +11,14 @@ row pass (last template argument 5) makes either the FP32 inner iteration or,
 once an inner loop has stopped, the FP64 outer update: its launches above 1.6x
 the median (duration, or counter value) are listed apart as ``<kernel>:outer``.
 
+``counters`` reads the ``<prefix>_counter_collection.csv`` of one ``--pmc`` run
+and prints, per kernel, the average of every listed counter over the working
+dispatches, chosen (and the mixed row pass's outer updates split off) by the
+first listed counter, e.g. SQ_WAVE_CYCLES: a launch that found its slot finished
+has all its waves exit at once.
+
+    python -m paper_2305_03945_amd.profsum counters <dir> <prefix> <counter> [<counter> ...]
+
 ``traffic`` reads the ``<prefix>_counter_collection.csv`` of two ``--pmc`` runs
 (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) and scales both by what the same
 counter reads for the calibration copy (``bench.py --calib-copy-mb``: a float32
@@ -88,6 +96,28 @@ def counter_table(path, counter):
     return out
 
 
+def counters_table(path, counters):
+    """kernel -> {counter: average over working dispatches, dispatches, working}; the
+    working dispatches and the outer-update split follow counters[0]."""
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        c = r.get("Counter_Name")
+        if c not in counters:
+            continue
+        d = vals.setdefault(short_name(r["Kernel_Name"]), {}).setdefault(r["Dispatch_Id"], {})
+        d[c] = d.get(c, 0.0) + float(r["Counter_Value"])
+    by = _split_outer({k: {i: d.get(counters[0], 0.0) for i, d in disp.items()} for k, disp in vals.items()})
+    out = {}
+    for k, sel in by.items():
+        disp = vals[k[:-len(":outer")] if k.endswith(":outer") else k]
+        med = statistics.median(sel.values())
+        ids = [i for i, v in sel.items() if v >= 0.5 * med]
+        row = {c: sum(disp[i].get(c, 0.0) for i in ids) / len(ids) for c in counters}
+        row.update(dispatches=len(sel), working=len(ids))
+        out[k] = row
+    return out
+
+
 def _code_only(text):
     """Source text without // comments and blank lines (comments do not change kernels)."""
     out = []
@@ -119,6 +149,16 @@ def main(argv):
             print("| %s | %d | %.1f | %d | %.1f | %.1f | %.1f |" % (r["kernel"], r["calls"], r["avg_us"],
                                                                r["working_calls"], r["working_avg_us"],
                                                                r["min_us"], r["max_us"]))
+        return
+    if argv[0] == "counters":
+        d, prefix, counters = argv[1], argv[2], argv[3:]
+        t = counters_table(os.path.join(d, prefix + "_counter_collection.csv"), counters)
+        print("| kernel | working dispatches | " + " | ".join(counters) + " |")
+        print("|---|---|" + "---|" * len(counters))
+        for k in sorted(t):
+            print("| %s | %d | " % (k, t[k]["working"]) + " | ".join("%.0f" % t[k][c] for c in counters) + " |")
+        print()
+        print(json.dumps(dict(source_hash=source_hash(), kernels=t)))
         return
     if argv[0] == "traffic":
         fdir, wdir, prefix, copy_bytes = argv[1], argv[2], argv[3], float(argv[4])

@@ -65,6 +65,27 @@ def test_traffic_scaling_by_the_calibration_copy(tmp_path):
     assert abs(js["kernels"]["k_upd<float,11,0,0,1>"]["hbm_bytes"] - (100 * 1024 * 2 + 50 * 1024)) < 1e-6
 
 
+def test_counters_average_working_dispatches_by_the_first_counter(tmp_path):
+    k = "void rdk::k_row_forward<float, 11, 0, 0, 5>(rdk::Slot* const*)"
+    rows = []
+    # four inner launches (cycles 100, instructions 10), one outer update (cycles 300,
+    # instructions 40) and one launch that found the slot finished (cycles 2)
+    for i, (cyc, ins) in enumerate([(100, 10)] * 4 + [(300, 40), (2, 0)]):
+        rows += [(i, "SQ_WAVE_CYCLES", cyc), (i, "SQ_INSTS_VALU", ins)]
+    other = "rdk::k_copy_out(rdk::Slot* const*, double*, unsigned long)"
+    with open(tmp_path / "x_counter_collection.csv", "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for i, c, v in rows:
+            f.write('%d,"%s",%s,%d\n' % (i, k, c, v))
+        f.write('9,"%s",SQ_WAVE_CYCLES,7\n' % other)
+    t = profsum.counters_table(str(tmp_path / "x_counter_collection.csv"), ["SQ_WAVE_CYCLES", "SQ_INSTS_VALU"])
+    assert t["rdk::k_copy_out"]["SQ_WAVE_CYCLES"] == 7
+    inner, outer = t["k_row_forward<float,11,0,0,5>"], t["k_row_forward<float,11,0,0,5>:outer"]
+    assert inner["dispatches"] == 5 and inner["working"] == 4
+    assert inner["SQ_WAVE_CYCLES"] == 100 and inner["SQ_INSTS_VALU"] == 10
+    assert outer["working"] == 1 and outer["SQ_INSTS_VALU"] == 40
+
+
 def test_source_hash_ignores_comments(tmp_path):
     a, b = tmp_path / "a", tmp_path / "b"
     a.mkdir()

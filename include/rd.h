@@ -58,7 +58,7 @@ typedef enum { RD_BC_PERIODIC = 0, RD_BC_NEUMANN = 1 } rd_bc;
  * a 3-D grid the 7-point Laplacian.
  * RD_OP_BIHARM13: -lambda Lap Lap with the 13-point stencil (= 5-point squared; Sec. 3.2).
  * RD_OP_FCH6: the sixth-order functionalized Cahn-Hilliard operator of Sec. 3.3 (nested
- * 5-point Laplacians, 25-point reach), with RD_RX_FCH only; FP64 precision only.        */
+ * 5-point Laplacians, 25-point reach), with RD_RX_FCH only.                             */
 typedef enum { RD_OP_LAP5 = 0, RD_OP_BIHARM13 = 1, RD_OP_FCH6 = 2 } rd_operator;
 
 /* Reaction term.  Parameters in rd_problem.p[]:
@@ -218,7 +218,7 @@ rd_status rd_residual(rd_ctx *ctx, const rd_problem *prob, double h_t, const dou
 /* Y = G^-1 W with G = (I - alpha Lap + beta Lap^2 - gamma Lap^3)^2 per component as the
  * equation implies (Sec. 2.1 "Choosing the matrix G"; Remark 1 for Neumann; Sec. 3.3 for
  * gamma).  w, y: DEVICE, [c][N][N] or [c][N][N][N].  precision RD_FP64 or RD_FP32_MIXED
- * (FP32 transforms; FP64 only for RD_OP_FCH6).  Synchronises.                               */
+ * (FP32 transforms).  Synchronises.                                                        */
 rd_status rd_precond_solve(rd_ctx *ctx, const rd_problem *prob, double h_t, int32_t precision,
                            const double *w, double *y, void *hip_stream);
 /* Pointwise reaction prox (the implicit reaction-only step, a predictor for U_0;

@@ -163,6 +163,11 @@ __device__ __forceinline__ void eval_F(SlotRef s, Acc u, const V *ukc, V *W, V *
 //   Allen-Cahn:   f(U+e) - f(U) = b (e - 3U^2 e - 3U e^2 - e^3)
 //   Cahn-Hilliard: g(U+e) - g(U) = b (3U^2 e + 3U e^2 + e^3 - e)  (under Lap)
 //   Schnakenberg: (U+e_u)^2 (V+e_v) - U^2 V = 2UV e_u + U^2 e_v + V e_u^2 + 2U e_u e_v + e_u^2 e_v
+//   FCH (Sec. 3.3): with mu(U) = eps^2 Lap U - W1(U), nu = eps^2 Lap mu - W2(U) mu + eps^2 mu,
+//     d_mu = eps^2 Lap e - (W1(U+e) - W1(U)),  W1(U+e) - W1(U) = 3U^2 e + 3U e^2 + e^3 - e,
+//     d_nu = eps^2 Lap d_mu + eps^2 d_mu - W2(U+e) d_mu - (W2(U+e) - W2(U)) mu(U),
+//     W2(U+e) - W2(U) = 6U e + 3e^2,  and F~ = r + e - h_t Lap d_nu
+//   (e on the 25-point reach, U on the 13-point one).
 // e: accessor of the correction, ub: accessor of the FP32 copy of U.
 template <int EQ, class AccE, class AccU>
 __device__ __forceinline__ void eval_Ftilde(SlotRef s, AccE e, AccU ub, const float *rc, float *W) {
@@ -184,6 +189,23 @@ __device__ __forceinline__ void eval_Ftilde(SlotRef s, AccE e, AccU ub, const fl
         const float lapdg = (dg(ub(0, 0, -1), el) + dg(ub(0, 0, 1), er) + dg(ub(0, -1, 0), eu) +
                              dg(ub(0, 1, 0), ed) - 4.0f * dg(ub(0, 0, 0), e0)) * ih2;
         W[0] = rc[0] + e0 + (float)s.diff[0] * ht * lap13 - ht * lapdg;
+    } else if constexpr (EQ == EQ_FCH) {
+        const float e2 = (float)s.diff[0];
+        auto ev = [&](int dy, int dx) { return e(0, dy, dx); };
+        auto uv = [&](int dy, int dx) { return ub(0, dy, dx); };
+        auto lap = [&](auto f, int dy, int dx) {
+            return (f(dy, dx - 1) + f(dy, dx + 1) + f(dy - 1, dx) + f(dy + 1, dx) - 4.0f * f(dy, dx)) * ih2;
+        };
+        auto dmu = [&](int dy, int dx) {
+            const float E = ev(dy, dx), U = uv(dy, dx);
+            return e2 * lap(ev, dy, dx) - (3.0f * U * U * E + 3.0f * U * E * E + E * E * E - E);
+        };
+        auto dnu = [&](int dy, int dx) {
+            const float E = ev(dy, dx), U = uv(dy, dx), d = dmu(dy, dx), V = U + E;
+            const float muU = e2 * lap(uv, dy, dx) - (U * U * U - U);
+            return e2 * lap(dmu, dy, dx) + e2 * d - (3.0f * V * V - 1.0f) * d - (6.0f * U * E + 3.0f * E * E) * muU;
+        };
+        W[0] = rc[0] + ev(0, 0) - ht * lap(dnu, 0, 0);
     } else {
         const float eu0 = e(0, 0, 0), ev0 = e(1, 0, 0);
         const float U = ub(0, 0, 0), Vv = ub(1, 0, 0);
@@ -314,6 +336,10 @@ template <typename T> __device__ __forceinline__ void store4(gptr_t<T> p, const 
 }
 
 template <int EQ> constexpr int stencil_hy() { return EQ == EQ_FCH ? 3 : EQ == EQ_BIH ? 2 : 1; }
+// Reach of the FP32 copy of U in the mixed inner residual: Cahn-Hilliard needs it at
+// the 5-point neighbours (reaction under Lap), FCH on the 13-point neighbourhood
+// (mu(U) under Lap, and the reaction difference under Lap^2); the others at the point.
+template <int EQ> constexpr int ftilde_hu() { return EQ == EQ_FCH ? 2 : EQ == EQ_BIH ? 1 : 0; }
 
 // ---------------------------------------------------------------- deterministic block sums
 // Workgroup sum of K values per thread, in a fixed order (wave butterflies, then
@@ -543,9 +569,7 @@ __device__ __forceinline__ void produce_W4(SlotRef s, StateRef sst, int y, int x
         }
     } else {
         static_assert(KIND == K_INNER32, "vectorised producer: iteration kinds only");
-        // Cahn-Hilliard needs U at the 5-point neighbours (reaction under Lap);
-        // the others only at the point.
-        constexpr int HU = EQ == EQ_BIH ? 1 : 0;
+        constexpr int HU = ftilde_hu<EQ>();
         const auto E = gp((const float *)s.U[(it + 1) & 1]);
         const auto Ub = gp((const float *)s.Ub32);
         Win<float, HY> we[C];
@@ -668,7 +692,7 @@ __device__ __forceinline__ void produce_W4x2(SlotRef s, StateRef sst, int y, int
                 }
             }
     } else {
-        constexpr int HU = EQ == EQ_BIH ? 1 : 0;
+        constexpr int HU = ftilde_hu<EQ>();
         const auto E = gp((const float *)s.U[(it + 1) & 1]);
         const auto Ub = gp((const float *)s.Ub32);
         Win2<float, HY> we[C];
@@ -1234,15 +1258,32 @@ __global__ __launch_bounds__(NT) void k_upd(Slot *const *slots) {
     vec4_t<T> un[C];
     T Uc[UPD_PPT][C];
     if constexpr (EQ == EQ_FCH) {
-        // the FCH adjoint also needs U on the 5-point neighbourhood (FP64 path only)
-        Win<T, 1> wu;
+        // the FCH adjoint also needs U on the 5-point neighbourhood: the FP64 iterate,
+        // or in the mixed inner loop U + e (the FP32 copy of U plus the correction)
+        Win<T, 1> wu, we;
         load_win<T, BC, LOGN, HY>(wp[0], Pt, y, x0);
-        load_win<T, BC, LOGN, 1>(wu, Ucur, y, x0);
+        if constexpr (MODE == MODE_F64) {
+            load_win<T, BC, LOGN, 1>(wu, Ucur, y, x0);
+            we = wu;
+        } else {
+            Win<float, 1> wub;
+            load_win<float, BC, LOGN, 1>(wub, gp((const float *)s.Ub32), y, x0);
+            if (it > 0) load_win<T, BC, LOGN, 1>(we, Ucur, y, x0);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int hx = i == 1 ? 1 : 0;
+#pragma unroll
+                for (int j = 1 - hx; j < 5 + hx; ++j) {
+                    if (it == 0) we.v[i][j] = (T)0;
+                    wu.v[i][j] = (T)wub.v[i][j] + we.v[i][j];
+                }
+            }
+        }
         const T tu = (T)s.tau_u;
         vec4_t<T> o;
 #pragma unroll
         for (int k = 0; k < UPD_PPT; ++k)
-            o[k] = wu.at(k, 0, 0) - tu * eval_adjoint_fch<T>(s, [&](int, int dy, int dx) { return wp[0].at(k, dy, dx); },
+            o[k] = we.at(k, 0, 0) - tu * eval_adjoint_fch<T>(s, [&](int, int dy, int dx) { return wp[0].at(k, dy, dx); },
                                                              [&](int, int dy, int dx) { return wu.at(k, dy, dx); });
         store4<T>(Unext + g0, o);
         return;

@@ -107,8 +107,7 @@ template <int BC, int EQ> void fill() {
     f.tout = launch_tout<double, BC, EQ>;
     f.rows_per_block = row_block<double, EQ>();
     if constexpr (wg_step_available<double, L, EQ>()) f.step_wg = launch_step_wg<double, BC, EQ, MODE_F64>;
-    // The FCH equation has no mixed-precision form (FP64 only).
-    if constexpr (EQ != EQ_FCH) fill_mixed<BC, EQ>();
+    fill_mixed<BC, EQ>();
 }
 
 template <int BC, int EQ> void fill_mixed() {

@@ -852,11 +852,13 @@ __device__ __forceinline__ void row_forward_pass(SlotRef s, StateRef sst, cplx<T
 #pragma unroll
     for (int k = 0; k < 2 * C; ++k) acc[k] = 0.0;
 
-    if constexpr (KIND == K_ITER64 || KIND == K_OUTER_UPD) {
+    if constexpr (KIND == K_ITER64 || KIND == K_OUTER_UPD || (KIND == K_INNER32 && LOGN >= 12)) {
         // four consecutive points of both rows of a pair per thread: the packed
         // complex value (row 2p + i row 2p+1) goes to LDS in one write.  The FP64
-        // iteration (2048^2: 27.7 -> 25.2 us) and the mixed outer update; the FP32
-        // inner pass measured no gain.
+        // iteration (2048^2: 27.7 -> 25.2 us), the mixed outer update, and the FP32
+        // inner pass at 4096^2, whose one-row windows re-fetch the stencil rows they
+        // share once the rows in flight exceed the L2 (75 -> 71 us); at 2048^2 the
+        // FP32 inner pass measured no gain.
 #pragma unroll 2
         for (int idx = threadIdx.x; idx < (R / 2) * N / 4; idx += NT) {
             const int p = idx >> (LOGN - 2), x0 = (idx & (N / 4 - 1)) * 4;

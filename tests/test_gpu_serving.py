@@ -220,11 +220,12 @@ def test_poll_and_argument_errors(rd):
 
 
 def test_fch_and_3d_trajectories_in_the_mix(rd):
-    """Sixth-order (FP64) and 3-D trajectories served beside 2-D ones: each result equals
-    its steps run alone through rd_step, bitwise, with the same iteration counts."""
+    """Sixth-order (FP64 and mixed) and 3-D trajectories served beside 2-D ones: each result
+    equals its steps run alone through rd_step, bitwise, with the same iteration counts."""
     import math
     fch = rd.make_problem("fch", 64, L=2 * math.pi, diff=(0.18 ** 2,))
     fch_o = rd.make_opts(tol=1e-6, tau_u=0.58, tau_p=0.58, max_iter=5000)
+    fch_m = rd.make_opts(tol=1e-6, tau_u=0.58, tau_p=0.58, max_iter=5000, precision="mixed")
     x = np.arange(64) * (2 * math.pi / 64)
     X, Y = np.meshgrid(x, x)
     fch_u0 = 2 * np.exp(np.sin(X) + np.sin(Y) - 2) + 2.2 * np.exp(-np.sin(X) - np.sin(Y) - 2) - 1
@@ -233,7 +234,7 @@ def test_fch_and_3d_trajectories_in_the_mix(rd):
     o3 = opts_for(rd, c3, "mixed")
     u3 = wl.uniform_field(32, -0.5, 0.5, 44, 3)
     c2 = small_cfg("schnakenberg", 64, "periodic")
-    jobs = [(fch, fch_o, fch_u0, (1e-3, 1e-3)), (p3, o3, u3, (1e-3, 2e-3)),
+    jobs = [(fch, fch_o, fch_u0, (1e-3, 1e-3)), (fch, fch_m, fch_u0, (1e-3, 2e-3)), (p3, o3, u3, (1e-3, 2e-3)),
             (rd.problem_from_config(c2), opts_for(rd, c2, "mixed"), wl.initial_field(c2, N=64, seed=45), (1e-3,))]
     alone = []
     actx = rd.Context(0)

@@ -56,6 +56,25 @@ def test_noalloc_step_matches_rd_step(ctx, rd, kind, bc, precision, bar):
         assert torch.equal(out, ref)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_noalloc_fch_step_matches_rd_step(ctx, rd, precision):
+    """The sixth-order equation (Sec. 3.3) through the allocation-free step, 128^2 then 64^2."""
+    import math
+    import torch
+    for N in (128, 64):
+        p = rd.make_problem("fch", N, L=2 * math.pi, diff=(0.18 ** 2,))
+        o = rd.make_opts(tol=1e-6, tau_u=0.58, tau_p=0.58, max_iter=5000, precision=precision)
+        x = np.arange(N) * (2 * math.pi / N)
+        X, Y = np.meshgrid(x, x)
+        u = dev(2 * np.exp(np.sin(X) + np.sin(Y) - 2) + 2.2 * np.exp(-np.sin(X) - np.sin(Y) - 2) - 1)
+        ref, info_ref = ctx.step(u, 1e-3, p, o)
+        out = torch.full_like(u, float("nan"))
+        info, code = ctx.step_noalloc(u, 1e-3, p, o, out)
+        assert code == rd.RD_OK and info["status"] == info_ref["status"] == "ok"
+        assert info["iters"] == info_ref["iters"] and info["outer"] == info_ref["outer"]
+        assert torch.equal(out, ref)
+
+
 def test_noalloc_in_place_and_refusal(ctx, rd):
     import torch
     cfg = small_cfg("allen_cahn", 128, "periodic")

@@ -93,6 +93,13 @@ typedef struct {
     double p[4];             /* reaction parameters, see rd_reaction_kind                   */
 } rd_problem;
 
+/* RD_FP32_MIXED: FP64 outer residual correction around an FP32 inner PDHG loop on the
+ * correction (the paper is silent on precision).  Its range: the FP32 evaluation of the
+ * inner residual must resolve the correction, i.e. 2^-24 times the linear stencil's weight
+ * relative to the identity (8 lambda h_t / h^2 for second-order operators, 64 lambda h_t / h^4
+ * for RD_OP_BIHARM13, 512 eps^4 h_t / h^6 for RD_OP_FCH6) well below 1; beyond it (e.g.
+ * Cahn-Hilliard at lambda = 4e-4, h_t = 1e-4 on 2048^2, FCH at the Sec. 3.3 parameters on
+ * 256^2) the inner loop diverges and the step returns RD_E_NONFINITE: use RD_FP64 there. */
 typedef enum { RD_FP64 = 0, RD_FP32_MIXED = 1 } rd_precision;
 typedef enum { RD_INIT_PREV = 0, RD_INIT_PROX = 1 } rd_init;
 

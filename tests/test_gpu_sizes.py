@@ -1,0 +1,102 @@
+"""Every equation on the grid sizes the parity tests leave out, through the C ABI, by
+properties that hold at any size: one implicit step in each precision and boundary
+condition ends with status ok, its result is finite, and the residual norm that the
+residual kernel (itself checked element by element against the oracle up to 2048^2)
+computes from the result equals the norm the step reported and meets the tolerance.
+The tolerance is 1e-3 of the step's initial residual norm, which keeps it well above
+the FP64 round-off floor of the plain norm at every size (the floor scales with the
+operator, as the initial norm does)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2305_03945_amd import workloads as wl
+from tests.rd_cases import small_cfg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_03945_amd import rd as rdmod
+    return rdmod
+
+
+@pytest.fixture(scope="module")
+def ctx(rd):
+    c = rd.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def case(rd, kind, N, bc):
+    """(problem, U^k, h_t, tau) of one equation on an N x N grid."""
+    if kind == "fch":
+        h = 2 * math.pi / N
+        x = (np.arange(N) + (0.5 if bc == "neumann" else 0.0)) * h
+        X, Y = np.meshgrid(x, x)
+        u0 = 2 * np.exp(np.sin(X) + np.sin(Y) - 2) + 2.2 * np.exp(-np.sin(X) - np.sin(Y) - 2) - 1
+        return rd.make_problem("fch", N, L=2 * math.pi, bc=bc, diff=(0.18 ** 2,)), u0, 1e-3, 0.58
+    base = {"heat": "allen_cahn", "biharmonic": "cahn_hilliard"}.get(kind, kind)
+    cfg = small_cfg(base, N, bc)
+    cfg["kind"] = kind
+    return rd.problem_from_config(cfg), wl.initial_field(cfg, N=N, seed=N + 3), cfg["ht"], cfg["tau"]
+
+
+CASES = [("cahn_hilliard", 1024), ("cahn_hilliard", 2048), ("cahn_hilliard", 4096), ("schnakenberg", 2048),
+         ("schnakenberg", 4096), ("heat", 2048), ("biharmonic", 1024), ("fch", 256), ("fch", 1024)]
+# Beyond the FP32 range of the mixed inner loop: 2^-24 times the linear stencil's weight
+# relative to the identity (Cahn-Hilliard 64 lambda h_t / h^4, FCH 512 eps^4 h_t / h^6) is
+# about 2.7 and 43 for Cahn-Hilliard at 2048^2 and 4096^2, 0.15 and 600 for FCH at 256^2
+# and 1024^2: the FP32 inner loop diverges there, and the step must say so.
+FP32_RANGE = {("cahn_hilliard", 2048), ("cahn_hilliard", 4096), ("fch", 256), ("fch", 1024)}
+# Where the method itself diverges at this h_t (the oracle too, see below).
+METHOD_DIVERGES = {("fch", 1024)}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+@pytest.mark.parametrize("kind,N", CASES)
+def test_step_on_untested_sizes(ctx, rd, kind, N, bc, precision):
+    import torch
+    p, u0_np, ht, tau = case(rd, kind, N, bc)
+    u0 = dev(u0_np)
+    _, r0 = ctx.residual(u0, u0, ht, p)
+    tol = 1e-3 * r0
+    o = rd.make_opts(tol=tol, tau_u=tau, tau_p=tau, max_iter=4000, precision=precision)
+    u1, info = ctx.step(u0, ht, p, o)
+    print("%s %d %s %s: iters %d outer %d residual %.3e (r0 %.3e)" % (kind, N, bc, precision, info["iters"],
+          info["outer"], info["residual"], r0), flush=True)
+    if (kind, N) in METHOD_DIVERGES or (precision == "mixed" and (kind, N) in FP32_RANGE):
+        # the divergence guard ends the step early and reports it
+        assert info["status"] == "nonfinite" and info["iters"] < 100, info
+        return
+    assert info["status"] == "ok", info
+    assert bool(torch.isfinite(u1).all())
+    _, r1 = ctx.residual(u1, u0, ht, p)
+    assert r1 <= tol * (1 + 1e-6)
+    assert r1 == pytest.approx(info["residual"], rel=1e-6)
+
+
+def test_fch_1024_diverges_like_the_oracle(ctx, rd):
+    """FCH at 1024^2 with h_t = 1e-3 (the Sec. 3.3 parameters on a grid 8 times finer):
+    Algorithm 1 itself diverges, and the FP64 step stops at the same iteration as the
+    oracle's, with the same status."""
+    from oracle import equations as oeq, grid, pdhg
+    N = 1024
+    op = oeq.Problem(kind=oeq.FCH, N=N, L=2 * math.pi, bc=grid.PERIODIC, diff=(0.18 ** 2,))
+    p, u0_np, ht, tau = case(rd, "fch", N, "periodic")
+    r0 = oeq.residual_norm(op, oeq.F(op, u0_np, u0_np, ht), ht)
+    ref = pdhg.step(op, u0_np, ht, pdhg.Options(tol=1e-3 * r0, tau_u=tau, tau_p=tau, max_iter=4000))
+    _, info = ctx.step(dev(u0_np), ht, p, rd.make_opts(tol=1e-3 * r0, tau_u=tau, tau_p=tau, max_iter=4000))
+    assert ref.status == pdhg.NONFINITE and info["status"] == "nonfinite"
+    assert info["iters"] == ref.iters

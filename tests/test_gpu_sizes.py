@@ -87,6 +87,36 @@ def test_step_on_untested_sizes(ctx, rd, kind, N, bc, precision):
     assert r1 == pytest.approx(info["residual"], rel=1e-6)
 
 
+def cfg3(kind, N, bc):
+    """3-D parameters: Schnakenberg as in the 1024^2 workload, heat with lambda = 0.05^2."""
+    if kind == "schnakenberg":
+        return dict(kind=kind, dim=3, N=N, L=1.0, bc=bc, diff=(1.0, 10.0), a=0.1, sb=0.9, kappa=1.0, ht=1e-3,
+                    init=("steady_plus_uniform", -0.05, 0.05), seed=N + 5, tol=1e-6, tau=0.9, omega=1.0)
+    return dict(kind=kind, dim=3, N=N, L=1.0, bc=bc, diff=(0.05 ** 2,), b=1.0, ht=1e-2,
+                init=("uniform", -0.9, 0.9), seed=N + 5, tol=1e-8, tau=0.9, omega=1.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+@pytest.mark.parametrize("kind,N", [("schnakenberg", 128), ("schnakenberg", 256), ("heat", 256)])
+def test_3d_step_on_untested_sizes(ctx, rd, kind, N, bc, precision):
+    """The same properties on 3-D grids the element-wise cases leave out."""
+    import torch
+    cfg = cfg3(kind, N, bc)
+    p = rd.problem_from_config(cfg)
+    u0 = dev(wl.initial_field(cfg))
+    # rd_residual takes 2-D grids only: the step's own initial norm sets the tolerance
+    o0 = rd.make_opts(tol=1e300, tau_u=cfg["tau"], tau_p=cfg["tau"], precision="fp64")
+    _, i0 = ctx.step(u0, cfg["ht"], p, o0)
+    tol = 1e-3 * i0["residual"]
+    o = rd.make_opts(tol=tol, tau_u=cfg["tau"], tau_p=cfg["tau"], max_iter=4000, precision=precision)
+    u1, info = ctx.step(u0, cfg["ht"], p, o)
+    print("3-D %s %d %s %s: iters %d outer %d residual %.3e (r0 %.3e)" % (kind, N, bc, precision, info["iters"],
+          info["outer"], info["residual"], i0["residual"]), flush=True)
+    assert i0["iters"] == 0 and info["status"] == "ok", info
+    assert info["residual"] <= tol and bool(torch.isfinite(u1).all())
+
+
 def test_fch_1024_diverges_like_the_oracle(ctx, rd):
     """FCH at 1024^2 with h_t = 1e-3 (the Sec. 3.3 parameters on a grid 8 times finer):
     Algorithm 1 itself diverges, and the FP64 step stops at the same iteration as the

@@ -130,3 +130,20 @@ def test_fch_1024_diverges_like_the_oracle(ctx, rd):
     _, info = ctx.step(dev(u0_np), ht, p, rd.make_opts(tol=1e-3 * r0, tau_u=tau, tau_p=tau, max_iter=4000))
     assert ref.status == pdhg.NONFINITE and info["status"] == "nonfinite"
     assert info["iters"] == ref.iters
+
+
+def test_fch_1024_recovers_with_adaptive_steps(ctx, rd):
+    """The remedy Sec. 2.2 proposes for a diverging step: with the adaptive step size the
+    same 1024^2 FCH problem rejects h_t = 1e-3, shrinks it, and reaches t = 2e-3 with every
+    accepted step at the tolerance."""
+    import torch
+    p, u0_np, ht, tau = case(rd, "fch", 1024, "periodic")
+    u = dev(u0_np)
+    _, r0 = ctx.residual(u, u, ht, p)   # F(U^k)/h_t does not depend on h_t here
+    o = rd.make_opts(tol=1e-3 * r0, tau_u=tau, tau_p=tau, max_iter=2000)
+    info, trace = ctx.advance(u, 2e-3, p, o, rd.make_adapt(1e-3, 0.5, 1000, 50))
+    print("adaptive FCH 1024:", info, trace[:12], flush=True)
+    assert info["status"] == "ok" and abs(info["t"] - 2e-3) < 1e-15
+    assert trace[0][0] == 1e-3 and not trace[0][2]          # the first try diverges and is rejected
+    assert all(h < 1e-3 for h, _, acc in trace if acc)     # every accepted step used a smaller h_t
+    assert bool(torch.isfinite(u).all())

@@ -7,6 +7,7 @@ fallback path.
 """
 import ctypes
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librdpdhg.so")
@@ -227,9 +228,12 @@ class Context:
         _check(_lib.rd_create(int(device), ctypes.byref(h)), "rd_create")
         self._h = h
         self.device = device
+        self._trajs = weakref.WeakSet()   # open trajectories: rd_destroy frees them
 
     def close(self):
         if self._h:
+            for t in list(self._trajs):
+                t._h = None
             _lib.rd_destroy(self._h)
             self._h = None
 
@@ -317,7 +321,9 @@ class Context:
         h = ctypes.c_void_p()
         _check(_lib.rd_traj_open(self._h, ctypes.byref(problem), ctypes.byref(opts), _dptr(u0, problem),
                                  _stream_ptr(stream), ctypes.byref(h)), "rd_traj_open")
-        return Trajectory(self, h, tuple(u0.shape))
+        t = Trajectory(self, h, tuple(u0.shape))
+        self._trajs.add(t)
+        return t
 
     def pump(self, max_wait_us=0):
         _check(_lib.rd_serve_pump(self._h, int(max_wait_us)), "rd_serve_pump")
@@ -346,16 +352,24 @@ class Trajectory:
         for n in shape:
             self.numel *= int(n)
 
+    def _handle(self, what):
+        # a trajectory closed, or freed with its context, has no handle left
+        if not self._h:
+            raise RDError(RD_E_INVALID, what)
+        return self._h
+
     def submit(self, ht):
+        h = self._handle("rd_traj_submit")
         t = ctypes.c_uint64()
-        _check(_lib.rd_traj_submit(self._h, float(ht), ctypes.byref(t)), "rd_traj_submit")
+        _check(_lib.rd_traj_submit(h, float(ht), ctypes.byref(t)), "rd_traj_submit")
         return t.value
 
     def read(self, out=None, stream=None):
         import torch
+        h = self._handle("rd_traj_read")
         if out is None:
             out = torch.empty(self.shape, dtype=torch.float64, device="cuda")
-        _check(_lib.rd_traj_read(self._h, _dptr(out, numel=self.numel), _stream_ptr(stream)), "rd_traj_read")
+        _check(_lib.rd_traj_read(h, _dptr(out, numel=self.numel), _stream_ptr(stream)), "rd_traj_read")
         return out
 
     def close(self):

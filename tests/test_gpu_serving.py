@@ -215,8 +215,27 @@ def test_poll_and_argument_errors(rd):
         with pytest.raises(rd.RDError):
             t.submit(float("nan"))
         t.close()
+        with pytest.raises(rd.RDError):   # a closed trajectory has no handle left
+            t.submit(1e-3)
     finally:
         ctx.close()
+
+
+def test_trajectory_outliving_its_context(rd):
+    """Closing a context frees its trajectories: a trajectory object kept past that point
+    refuses to submit or read, and closing it is a no-op (no freed handle reaches the C
+    library)."""
+    ctx = rd.Context(0)
+    cfg = small_cfg("allen_cahn", 64, "periodic")
+    t = ctx.open(rd.problem_from_config(cfg), opts_for(rd, cfg, "fp64"), dev(wl.initial_field(cfg, N=64)))
+    t.submit(cfg["ht"])
+    ctx.close()
+    with pytest.raises(rd.RDError):
+        t.submit(cfg["ht"])
+    with pytest.raises(rd.RDError):
+        t.read()
+    t.close()
+    t.close()
 
 
 def test_fch_and_3d_trajectories_in_the_mix(rd):

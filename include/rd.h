@@ -284,7 +284,8 @@ rd_status rd_poll(rd_ctx *ctx, uint64_t ticket, rd_info *info);
 /* Copy the trajectory's current state U^k to u_out (DEVICE).  Synchronises.            */
 rd_status rd_traj_read(rd_traj *traj, double *u_out, void *hip_stream);
 /* Close a trajectory: waits for the device, releases its workspace (returning its bytes
- * to the budget) and its resident state.  Unfinished tickets of it stay RD_E_BUSY.      */
+ * to the budget), its resident state and its tickets: rd_poll then returns RD_E_INVALID
+ * for every ticket of it, finished or not (unfinished steps are dropped).                */
 rd_status rd_traj_close(rd_traj *traj);
 
 typedef struct {

@@ -251,6 +251,7 @@ struct Traj {
     double *u = nullptr;                 // resident state U^k (FP64)
     std::unique_ptr<Workspace> ws;       // present once admitted
     std::deque<PendingStep> pending;
+    std::vector<uint64_t> tickets;       // every ticket of this trajectory; released at close
     bool running = false;
     uint64_t running_ticket = 0;
     int issued = 0;                      // iterations launched for the running step
@@ -1181,6 +1182,7 @@ rd_status rd_traj_submit(rd_traj *traj, double h_t, uint64_t *ticket) {
     Ctx *c = t->ctx;
     const uint64_t id = c->next_ticket++;
     c->tickets[id] = Ticket{};
+    t->tickets.push_back(id);
     t->pending.push_back(PendingStep{id, h_t});
     if (!t->ws && !t->queued_for_admission) {
         c->admit_queue.push_back(t);
@@ -1450,6 +1452,9 @@ rd_status rd_traj_close(rd_traj *traj) {
             c->trajs.erase(c->trajs.begin() + i);
             break;
         }
+    // its tickets, finished or not, become unknown: no poll waits on a step that will
+    // never run, and the ticket table holds the open trajectories' steps only
+    for (uint64_t id : t->tickets) c->tickets.erase(id);
     if (t->u) (void)hipFree(t->u);
     delete t;
     return RD_OK;

@@ -505,10 +505,41 @@ void serving() {
         }
     }
     CHECK(closed == (int)ts.size());
+    // a closed trajectory's tickets are released
+    for (T &t : ts) CHECK(rd_poll(ctx, t.tickets[0], &info) == RD_E_INVALID);
     rd_serve_info si;
     rd_serve_stats(ctx, &si);
     CHECK(si.admitted == 0 && si.resident_bytes == 0 && si.queued == 0 && si.running == 0);
     for (T &t : ts) hipFree(t.u);
+    rd_destroy(ctx);
+}
+
+// Closing a trajectory with steps still queued drops them: their tickets become
+// unknown instead of staying busy, and the other trajectories' steps complete.
+void close_with_pending_steps() {
+    rd_ctx *ctx = nullptr;
+    rd_create(0, &ctx);
+    rd_problem p = ac(16);
+    rd_opts o = opts(1e-3, RD_FP64);
+    double *u = dalloc(256);
+    for (int i = 0; i < 256; ++i) u[i] = 0.5;
+    rd_traj *a = nullptr, *b = nullptr;
+    CHECK(rd_traj_open(ctx, &p, &o, u, nullptr, &a) == RD_OK);
+    CHECK(rd_traj_open(ctx, &p, &o, u, nullptr, &b) == RD_OK);
+    uint64_t ta[3], tb = 0;
+    for (uint64_t &tk : ta) CHECK(rd_traj_submit(a, 0.01, &tk) == RD_OK);
+    CHECK(rd_traj_submit(b, 0.01, &tb) == RD_OK);
+    rd_info info;
+    CHECK(rd_serve_pump(ctx, 0) == RD_OK);   // a's first step and b's step start
+    CHECK(rd_traj_close(a) == RD_OK);
+    for (uint64_t tk : ta) CHECK(rd_poll(ctx, tk, &info) == RD_E_INVALID);
+    for (int k = 0; k < 100 && rd_poll(ctx, tb, &info) == RD_E_BUSY; ++k) CHECK(rd_serve_pump(ctx, 0) == RD_OK);
+    CHECK(rd_poll(ctx, tb, &info) == RD_OK && info.iters == model_iters(0.01, 1e-3));
+    rd_serve_info si;
+    rd_serve_stats(ctx, &si);
+    CHECK(si.queued == 0 && si.running == 0);
+    CHECK(rd_traj_close(b) == RD_OK);
+    hipFree(u);
     rd_destroy(ctx);
 }
 
@@ -657,6 +688,7 @@ int main() {
     fp64_steps();
     mixed_steps();
     serving();
+    close_with_pending_steps();
     adaptive();
     column_pass_race_invariant();
     noalloc_steps();

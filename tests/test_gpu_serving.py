@@ -238,6 +238,33 @@ def test_trajectory_outliving_its_context(rd):
     t.close()
 
 
+def test_close_drops_queued_steps(rd):
+    """Closing a trajectory with steps still queued releases their tickets (polling one
+    raises instead of staying busy), and another trajectory's step still completes with
+    the result it has alone."""
+    ctx = rd.Context(0)
+    try:
+        cfg = small_cfg("allen_cahn", 64, "periodic")
+        p, o = rd.problem_from_config(cfg), opts_for(rd, cfg, "fp64")
+        u0 = wl.initial_field(cfg, N=64)
+        a = ctx.open(p, o, dev(u0))
+        b = ctx.open(p, o, dev(u0))
+        ta = [a.submit(cfg["ht"]) for _ in range(3)]
+        tb = b.submit(cfg["ht"])
+        ctx.pump()
+        a.close()
+        for tk in ta:
+            with pytest.raises(rd.RDError):
+                ctx.poll(tk)
+        pump_until(ctx, lambda: ctx.poll(tb) is not None)
+        alone, info = ctx.step(dev(u0), cfg["ht"], p, o)
+        assert ctx.poll(tb)["iters"] == info["iters"]
+        assert np.array_equal(b.read().cpu().numpy(), alone.cpu().numpy())
+        b.close()
+    finally:
+        ctx.close()
+
+
 def test_fch_and_3d_trajectories_in_the_mix(rd):
     """Sixth-order (FP64 and mixed) and 3-D trajectories served beside 2-D ones: each result
     equals its steps run alone through rd_step, bitwise, with the same iteration counts."""

@@ -281,7 +281,9 @@ rd_status rd_serve_pump(rd_ctx *ctx, int32_t max_wait_us);
 /* RD_E_BUSY until the ticket's step finished; then fills info (HOST) and returns the
  * step's status.  RD_E_INVALID for an unknown ticket.                                   */
 rd_status rd_poll(rd_ctx *ctx, uint64_t ticket, rd_info *info);
-/* Copy the trajectory's current state U^k to u_out (DEVICE).  Synchronises.            */
+/* Copy the trajectory's current state U^k to u_out (DEVICE): the result of its last step
+ * finished by the end of any serving round in flight, which the copy waits for.
+ * Synchronises.                                                                         */
 rd_status rd_traj_read(rd_traj *traj, double *u_out, void *hip_stream);
 /* Close a trajectory: waits for the device, releases its workspace (returning its bytes
  * to the budget), its resident state and its tickets: rd_poll then returns RD_E_INVALID

@@ -3,6 +3,7 @@
 // the continuous-batching serving loop.  Implements include/rd.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1423,6 +1424,13 @@ rd_status rd_traj_read(rd_traj *traj, double *u_out, void *hip_stream) {
     Traj *t = (Traj *)traj;
     RD_CHECK(hipSetDevice(t->ctx->device));
     hipStream_t st = (hipStream_t)hip_stream;
+    // a round in flight that advances t replaces its resident state when a step
+    // finishes: the copy waits for that round, so it never sees a state half written
+    for (auto &kv : t->ctx->rounds) {
+        const GroupRound &g = kv.second;
+        if (g.in_flight && std::find(g.trajs.begin(), g.trajs.end(), t) != g.trajs.end())
+            RD_CHECK(hipStreamWaitEvent(st, g.done, 0));
+    }
     RD_CHECK(hipMemcpyAsync(u_out, t->u, field_bytes(t->d.pts, t->d.C, 8), hipMemcpyDeviceToDevice, st));
     RD_CHECK(hipStreamSynchronize(st));
     return RD_OK;

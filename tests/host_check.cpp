@@ -531,6 +531,9 @@ void close_with_pending_steps() {
     CHECK(rd_traj_submit(b, 0.01, &tb) == RD_OK);
     rd_info info;
     CHECK(rd_serve_pump(ctx, 0) == RD_OK);   // a's first step and b's step start
+    double *mid = dalloc(256);
+    CHECK(rd_traj_read(b, mid, nullptr) == RD_OK);   // waits for b's round, if in flight
+    hipFree(mid);
     CHECK(rd_traj_close(a) == RD_OK);
     for (uint64_t tk : ta) CHECK(rd_poll(ctx, tk, &info) == RD_E_INVALID);
     for (int k = 0; k < 100 && rd_poll(ctx, tb, &info) == RD_E_BUSY; ++k) CHECK(rd_serve_pump(ctx, 0) == RD_OK);

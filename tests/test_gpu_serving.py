@@ -265,6 +265,34 @@ def test_close_drops_queued_steps(rd):
         ctx.close()
 
 
+def test_read_while_a_round_runs(rd):
+    """A read issued while the trajectory's round is in flight returns a whole state: the
+    initial one or the result of a finished step, each bitwise as computed alone."""
+    ctx = rd.Context(0)
+    try:
+        cfg = small_cfg("allen_cahn", 256, "periodic")
+        p, o = rd.problem_from_config(cfg), opts_for(rd, cfg, "fp64")
+        u0 = wl.initial_field(cfg, N=256)
+        s1, _ = ctx.step(dev(u0), cfg["ht"], p, o)
+        s2, _ = ctx.step(s1.clone(), cfg["ht"], p, o)
+        whole = [u0, s1.cpu().numpy(), s2.cpu().numpy()]
+        t = ctx.open(p, o, dev(u0))
+        tickets = [t.submit(cfg["ht"]) for _ in range(2)]
+        seen = 0
+        for _ in range(MAX_PUMPS):
+            if all(ctx.poll(tk) is not None for tk in tickets):
+                break
+            ctx.pump()
+            r = t.read().cpu().numpy()
+            k = [i for i, w in enumerate(whole) if np.array_equal(r, w)]
+            assert k and k[0] >= seen, "read returned a state that is no step's result"
+            seen = k[0]
+        assert np.array_equal(t.read().cpu().numpy(), whole[2])
+        t.close()
+    finally:
+        ctx.close()
+
+
 def test_fch_and_3d_trajectories_in_the_mix(rd):
     """Sixth-order (FP64 and mixed) and 3-D trajectories served beside 2-D ones: each result
     equals its steps run alone through rd_step, bitwise, with the same iteration counts."""

@@ -271,7 +271,10 @@ rd_status rd_serve_set_budget(rd_ctx *ctx, size_t bytes);
 rd_status rd_traj_open(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts,
                        const double *u0, void *hip_stream, rd_traj **out);
 /* Queue one implicit step of size h_t; *ticket (HOST) identifies it.  Steps of one
- * trajectory run in submission order, each starting from the previous one's result.    */
+ * trajectory run in submission order, each starting from the trajectory's state: the
+ * result of its last step that ended RD_OK.  A step that fails (RD_E_NOCONV,
+ * RD_E_NONFINITE, reported by rd_poll) leaves that state unchanged, so that the caller
+ * may submit the step again with a smaller h_t.                                          */
 rd_status rd_traj_submit(rd_traj *traj, double h_t, uint64_t *ticket);
 /* One serving round: admits queued trajectories, retires the rounds that have completed,
  * starts a round for every idle group with work; if no round had completed, waits for the
@@ -282,8 +285,8 @@ rd_status rd_serve_pump(rd_ctx *ctx, int32_t max_wait_us);
  * step's status.  RD_E_INVALID for an unknown ticket.                                   */
 rd_status rd_poll(rd_ctx *ctx, uint64_t ticket, rd_info *info);
 /* Copy the trajectory's current state U^k to u_out (DEVICE): the result of its last step
- * finished by the end of any serving round in flight, which the copy waits for.
- * Synchronises.                                                                         */
+ * that ended RD_OK by the end of any serving round in flight, which the copy waits for
+ * (the initial state if none has).  Synchronises.                                       */
 rd_status rd_traj_read(rd_traj *traj, double *u_out, void *hip_stream);
 /* Close a trajectory: waits for the device, releases its workspace (returning its bytes
  * to the budget), its resident state and its tickets: rd_poll then returns RD_E_INVALID

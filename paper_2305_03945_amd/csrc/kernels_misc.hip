@@ -61,14 +61,19 @@ void launch_copy_out(Slot *const *slots, double *out, size_t n, hipStream_t st) 
     hipLaunchKernelGGL(k_copy_out, dim3(blocks), dim3(NT), 0, st, slots, out, n);
 }
 
-// Serving: the finished steps of a batch of slots (blockIdx.y) replace their
-// trajectories' resident states, which are the steps' inputs (src); a slot whose
-// step still runs is left alone.  The input is read only by the initial pass, so
-// once the step has finished it may be overwritten.
+// Serving: the steps of a batch of slots (blockIdx.y) that finished with status
+// ok replace their trajectories' resident states, which are the steps' inputs
+// (src); a slot whose step still runs, or failed (no convergence, not finite), is
+// left alone, so that the trajectory keeps U^k.  The input is read only by the
+// initial pass, so once the step has finished it may be overwritten.
 __global__ __launch_bounds__(NT) void k_copy_back(Slot *const *slots, size_t n) {
     SlotRef s = slot_of(slots);
     StateRef sst = state_of(s);
     if (!sst.outer_done) return;
+    __shared__ int sh_status;
+    if (threadIdx.x == 0) sh_status = ld_agent(&s.st->status);
+    __syncthreads();
+    if (sh_status != ST_OK) return;
     const double *src = s.mode == MODE_F64 ? (const double *)s.U[sst.iters & 1] : s.U64[sst.outer & 1];
     const auto in4 = gp((const vec4_t<double> *)src);
     const auto out4 = gp((vec4_t<double> *)const_cast<double *>(s.src));

@@ -253,7 +253,7 @@ void launch_copy_out(Slot *const *slots, double *out, size_t n, hipStream_t) {
 void launch_copy_back(Slot *const *slots, int nslots, size_t n, hipStream_t) {
     for (int i = 0; i < nslots; ++i) {
         const Slot &s = *slots[i];
-        if (!s.st->outer_done) continue;
+        if (!s.st->outer_done || s.st->status != ST_OK) continue;
         const double *src = s.mode == MODE_F64 ? (const double *)s.U[s.st->iters & 1] : s.U64[s.st->outer & 1];
         std::memmove(const_cast<double *>(s.src), src, n * sizeof(double));
     }

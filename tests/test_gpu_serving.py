@@ -293,6 +293,40 @@ def test_read_while_a_round_runs(rd):
         ctx.close()
 
 
+@pytest.mark.parametrize("N", [64, 256])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_failed_step_leaves_the_state(rd, N, precision):
+    """A served step that fails (here: the iteration limit) reports the status rd_step
+    reports alone and leaves the trajectory at U^k; a later step with room to converge
+    starts from U^k and gives the step's result alone."""
+    ctx = rd.Context(0)
+    try:
+        cfg = small_cfg("allen_cahn", N, "periodic")
+        p = rd.problem_from_config(cfg)
+        tight = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], max_iter=3, max_outer=1,
+                             precision=precision)
+        u0 = wl.initial_field(cfg, N=N)
+        _, alone = ctx.step(dev(u0), cfg["ht"], p, tight)
+        assert alone["status"] != "ok", alone
+        t = ctx.open(p, tight, dev(u0))
+        tk = t.submit(cfg["ht"])
+        pump_until(ctx, lambda: ctx.poll(tk) is not None)
+        info = ctx.poll(tk)
+        assert (info["status"], info["iters"], info["outer"]) == (alone["status"], alone["iters"], alone["outer"])
+        assert np.array_equal(t.read().cpu().numpy(), u0)
+        t.close()
+        o = opts_for(rd, cfg, precision)
+        t = ctx.open(p, o, dev(u0))
+        tk = t.submit(cfg["ht"])
+        pump_until(ctx, lambda: ctx.poll(tk) is not None)
+        ref, ref_info = ctx.step(dev(u0), cfg["ht"], p, o)
+        assert ctx.poll(tk)["status"] == ref_info["status"] == "ok"
+        assert np.array_equal(t.read().cpu().numpy(), ref.cpu().numpy())
+        t.close()
+    finally:
+        ctx.close()
+
+
 def test_fch_and_3d_trajectories_in_the_mix(rd):
     """Sixth-order (FP64 and mixed) and 3-D trajectories served beside 2-D ones: each result
     equals its steps run alone through rd_step, bitwise, with the same iteration counts."""

@@ -494,7 +494,7 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=8, help="steps per trajectory in the serving stream")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+        print("bench.py measures one GPU only: the library has no multi-GPU path (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

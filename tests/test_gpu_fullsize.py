@@ -166,6 +166,29 @@ def test_ac2048_sampled_residual_after_steps(ctx, rd):
     assert np.sqrt(np.sum((W / cfg["ht"]) ** 2)) <= cfg["tol"] * (1 + 1e-6)
 
 
+@pytest.fixture(scope="module")
+def ac4096_oracle_first():
+    """The oracle's first step of the 4096^2 Allen-Cahn measurement workload (about 40 s of
+    numpy on one host core)."""
+    cfg = wl.CONFIGS["ac4096"]
+    return opdhg.step(oracle_problem(cfg), wl.initial_field(cfg), cfg["ht"], oracle_opts(cfg))
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_ac4096_first_step_elementwise(ctx, rd, ac4096_oracle_first, precision, bar):
+    """The largest 2-D grid, beyond the last-level cache: the first step of the 4096^2
+    Allen-Cahn workload that the bench times, every grid point against the oracle's (FP64:
+    equal iteration counts)."""
+    cfg = wl.CONFIGS["ac4096"]
+    ref = ac4096_oracle_first
+    o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], omega=cfg["omega"], precision=precision)
+    u, info = ctx.step(dev(wl.initial_field(cfg)), cfg["ht"], rd.problem_from_config(cfg), o)
+    assert info["status"] == "ok", info
+    if precision == "fp64":
+        assert info["iters"] == ref.iters
+    assert max_abs(u.cpu().numpy(), ref.U) <= bar
+
+
 @pytest.mark.parametrize("bc", ["periodic", "neumann"])
 def test_largest_grid_step_4096(ctx, rd, bc):
     """The largest 2-D grid, one Allen-Cahn step in each precision: both stop at the

@@ -207,6 +207,28 @@ def test_largest_grid_step_4096(ctx, rd, bc):
     assert max_abs(out["fp64"], out["mixed"]) <= 1e-5
 
 
+@pytest.fixture(scope="module")
+def ac3d256_oracle_first():
+    """The oracle's first step of the 128^3 Allen-Cahn workload's parameters on 256^3, the
+    input the bench times there (about 40 s of numpy on one host core)."""
+    cfg = dict(wl.CONFIGS["ac3d128"], N=256)
+    return opdhg.step(oracle_problem(cfg), wl.initial_field(cfg), cfg["ht"], oracle_opts(cfg))
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_ac3d256_first_step_elementwise(ctx, rd, ac3d256_oracle_first, precision, bar):
+    """The largest 3-D grid: the first 256^3 step every grid point against the oracle's
+    (FP64: equal iteration counts)."""
+    cfg = dict(wl.CONFIGS["ac3d128"], N=256)
+    ref = ac3d256_oracle_first
+    o = rd.make_opts(tol=cfg["tol"], tau_u=cfg["tau"], tau_p=cfg["tau"], omega=cfg["omega"], precision=precision)
+    u, info = ctx.step(dev(wl.initial_field(cfg)), cfg["ht"], rd.problem_from_config(cfg), o)
+    assert info["status"] == "ok", info
+    if precision == "fp64":
+        assert info["iters"] == ref.iters
+    assert max_abs(u.cpu().numpy(), ref.U) <= bar
+
+
 @pytest.mark.parametrize("bc", ["periodic", "neumann"])
 def test_largest_grid_step_3d_256(ctx, rd, bc):
     """The largest 3-D grid (256^3), one Allen-Cahn step in each precision, checked the same way."""

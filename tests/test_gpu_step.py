@@ -327,6 +327,37 @@ def test_unaligned_output_buffer(ctx, rd, precision):
         assert np.all(rest == 7.0), off
 
 
+def test_two_contexts_interleaved(ctx, rd):
+    """Two contexts on one device, used in turn on problems that share grid sizes (so each
+    holds its own cached workspaces and tables for them): every result is bitwise the
+    result of the same steps on one context alone."""
+    import torch
+    cases = [(small_cfg("allen_cahn", 256, "periodic"), "fp64"), (small_cfg("allen_cahn", 256, "neumann"), "mixed"),
+             (small_cfg("schnakenberg", 64, "periodic"), "fp64"), (small_cfg("cahn_hilliard", 64, "neumann"), "mixed")]
+    runs = []
+    for cfg, prec in cases:
+        p, o = rd.problem_from_config(cfg), gpu_opts(rd, cfg, prec)
+        u0 = dev(wl.initial_field(cfg, N=cfg["N"], seed=cfg["N"] + 7))
+        runs.append((p, o, cfg["ht"], u0))
+    alone = []
+    for p, o, ht, u0 in runs:
+        u = u0
+        for _ in range(2):
+            u, _ = ctx.step(u, ht, p, o)
+        alone.append(u)
+    other = rd.Context(0)
+    try:
+        states = [[u0, u0] for _, _, _, u0 in runs]
+        for _ in range(2):
+            for i, (p, o, ht, _) in enumerate(runs):
+                states[i][0], _ = ctx.step(states[i][0], ht, p, o)
+                states[i][1], _ = other.step(states[i][1], ht, p, o)
+        for (a, b), ref in zip(states, alone):
+            assert torch.equal(a, ref) and torch.equal(b, ref)
+    finally:
+        other.close()
+
+
 def test_invalid_problems_rejected_before_any_device_work(ctx, rd):
     """Shapes and operator/reaction pairs the library does not take: rd_footprint_bytes
     is 0 and rd_step returns RD_E_INVALID, without touching the (one-value) buffers."""

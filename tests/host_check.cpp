@@ -546,6 +546,39 @@ void close_with_pending_steps() {
     rd_destroy(ctx);
 }
 
+// A served step that stops at the iteration limit reports RD_E_NOCONV and leaves the
+// trajectory's state; the next step of a trajectory with room to converge starts from it.
+void failed_step_leaves_state() {
+    rd_ctx *ctx = nullptr;
+    rd_create(0, &ctx);
+    rd_problem p = ac(16);
+    rd_opts tight = opts(1e-3, RD_FP64);
+    tight.max_iter = 2;
+    double *u = dalloc(256);
+    for (int i = 0; i < 256; ++i) u[i] = 0.5;
+    rd_traj *t = nullptr;
+    CHECK(rd_traj_open(ctx, &p, &tight, u, nullptr, &t) == RD_OK);
+    uint64_t tk = 0;
+    CHECK(rd_traj_submit(t, 0.01, &tk) == RD_OK);
+    rd_info info;
+    for (int k = 0; k < 100 && rd_poll(ctx, tk, &info) == RD_E_BUSY; ++k) CHECK(rd_serve_pump(ctx, 0) == RD_OK);
+    CHECK(rd_poll(ctx, tk, &info) == RD_E_NOCONV && info.status == RD_E_NOCONV);
+    double *out = dalloc(256);
+    CHECK(rd_traj_read(t, out, nullptr) == RD_OK && all_equal(out, 256, 0.5));
+    CHECK(rd_traj_close(t) == RD_OK);
+    // the same start, with room to converge: the model's iterate gains 1 per iteration
+    rd_opts o = opts(1e-3, RD_FP64);
+    CHECK(rd_traj_open(ctx, &p, &o, out, nullptr, &t) == RD_OK);
+    CHECK(rd_traj_submit(t, 0.01, &tk) == RD_OK);
+    for (int k = 0; k < 100 && rd_poll(ctx, tk, &info) == RD_E_BUSY; ++k) CHECK(rd_serve_pump(ctx, 0) == RD_OK);
+    CHECK(rd_poll(ctx, tk, &info) == RD_OK);
+    CHECK(rd_traj_read(t, out, nullptr) == RD_OK && all_equal(out, 256, 0.5 + model_iters(0.01, 1e-3)));
+    CHECK(rd_traj_close(t) == RD_OK);
+    hipFree(out);
+    hipFree(u);
+    rd_destroy(ctx);
+}
+
 void adaptive() {
     rd_adapt a{};
     a.ht0 = 0.02;
@@ -692,6 +725,7 @@ int main() {
     mixed_steps();
     serving();
     close_with_pending_steps();
+    failed_step_leaves_state();
     adaptive();
     column_pass_race_invariant();
     noalloc_steps();

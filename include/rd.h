@@ -155,10 +155,9 @@ rd_status rd_step(rd_ctx *ctx, const rd_problem *prob, const rd_opts *opts, doub
                   const double *u_n, double *u_np1, void *hip_stream, rd_info *info);
 
 /* ---- one implicit step without allocation ------------------------------------------ */
-/* For callers that cannot allocate device or pinned memory while they run (code that runs
- * while a graph capture forbids allocation, tight serving loops, harnesses that forbid
- * hipMalloc; the call itself waits on the host for each chunk's stop decision, so it is
- * not one that a captured graph can record): rd_step with
+/* For callers that cannot allocate device or pinned memory while they run (tight serving
+ * loops, harnesses that forbid hipMalloc; the call waits on the host for each chunk's stop
+ * decision, so a captured graph cannot record it): rd_step with
  * the same arguments, results and statuses (FP64 results bitwise equal to rd_step's; the
  * mixed path's within its rounding), whose workspace, tables, slot and State live in a
  * device scratch array of 64 MiB that the library holds on every device it runs on until
